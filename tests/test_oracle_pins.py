@@ -1,0 +1,371 @@
+"""Pins of the FP64 oracle against things other than itself (CPU only).
+
+Each test names what fixes the expected value: a plain definition written out
+independently (dense LU with explicit DFT matrices), a closed form (uniform
+medium per Fourier mode, 1D reduction, Fabry-Perot slab), an invariant
+(reciprocity, energy balance, mirror symmetry, shift independence) or brute
+force (finite differences, per-voxel loops).
+"""
+
+import cmath
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import cbs as oc
+from oracle import closed, dense
+from paper_2506_15411_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+LAM = 1.064e-6
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel())
+                 / max(np.linalg.norm(np.asarray(b).ravel()), 1e-300))
+
+
+def small_grid(shape, pml=(1, 1, 1), pitch=LAM / 6, **kw):
+    nx, ny, nz = shape
+    return oc.Grid(nx, ny, nz, pitch, LAM, 1.0, pml, **kw)
+
+
+# ---------------------------------------------------------------------------
+# Absorbing profile: per-voxel loops from the definition
+# ---------------------------------------------------------------------------
+def test_sigma_profile_bruteforce():
+    g = small_grid((7, 6, 9), pml=(2, 1, 3), sigma_max=0.8, pml_order=2)
+    sig = oc.absorber_sigma(g)
+
+    def u(i, n, p):
+        if p == 0:
+            return 0.0
+        if i < p:
+            return (p - i) / p
+        if i >= n - p:
+            return (i - (n - p - 1)) / p
+        return 0.0
+
+    for k in range(g.nz):
+        for j in range(g.ny):
+            for i in range(g.nx):
+                s = u(i, g.nx, 2) ** 2 + u(j, g.ny, 1) ** 2 + u(k, g.nz, 3) ** 2
+                assert sig[k, j, i] == pytest.approx(0.8 * min(1.0, s), abs=1e-15)
+    # interior is exactly zero and the outermost corner saturates
+    assert sig[3:6, 1:5, 2:5].max() == 0.0
+    assert sig[0, 0, 0] == pytest.approx(0.8)
+
+
+# ---------------------------------------------------------------------------
+# Green's tensor: explicit 3x3 inverse of M(p) - kt2 I
+# ---------------------------------------------------------------------------
+def test_green_tensor_is_inverse_of_curl_curl_symbol():
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=(200, 3)) * 1e7
+    pt = p.copy()
+    pt[::3, 0] = 0.0          # Nyquist-zeroed entries of the dyadic vector
+    pt[1::5, 2] = 0.0
+    kt2 = (2 * math.pi / LAM) ** 2 * (1.0 + 0.7j)
+    G = oc.green_tensor(p, pt, kt2)
+    M = (np.sum(p * p, -1)[:, None, None] * np.eye(3) - pt[:, :, None] * pt[:, None, :])
+    ref = np.linalg.inv(M - kt2 * np.eye(3))
+    assert rel(G, ref) < 1e-12
+    # where pt = p this is the dyadic form (I - p p^T / kt2) / (|p|^2 - kt2)
+    G2 = oc.green_tensor(p, p, kt2)
+    dy = (np.eye(3) - p[:, :, None] * p[:, None, :] / kt2) / (np.sum(p * p, -1) - kt2)[:, None, None]
+    assert rel(G2, dy) < 1e-12
+
+
+def test_frequencies_match_fft_order():
+    for n in (1, 2, 5, 6, 64, 275):
+        d = 1e-7
+        p, pt = oc.frequencies(n, d)
+        ref = 2 * math.pi * np.fft.fftfreq(n, d)
+        assert np.allclose(p, ref, rtol=0, atol=1e-9 * (1 + np.abs(ref).max()))
+        if n % 2 == 0:
+            assert pt[n // 2] == 0.0 and p[n // 2] < 0
+        assert np.count_nonzero(pt != p) == (1 if n % 2 == 0 else 0)
+
+
+# ---------------------------------------------------------------------------
+# Dense operator: DFT matrices vs the textbook FFT, symmetry of A
+# ---------------------------------------------------------------------------
+def test_dft_matrix_is_the_dft():
+    rng = np.random.default_rng(0)
+    for n in (2, 3, 5, 8, 12):
+        x = rng.normal(size=n) + 1j * rng.normal(size=n)
+        F = dense.dft_matrix(n)
+        naive = np.array([sum(x[j] * cmath.exp(-2j * math.pi * m * j / n) for j in range(n))
+                          for m in range(n)])
+        assert rel(F @ x, naive) < 1e-13
+
+
+@pytest.mark.parametrize("shape", [(4, 5, 6), (3, 4, 4)])
+def test_operator_is_complex_symmetric_and_L_hermitian(shape):
+    g = small_grid(shape, pml=(1, 1, 1))
+    L = dense.curl_curl_dense(g)
+    assert np.abs(L - L.T).max() < 1e-9 * np.abs(L).max()
+    assert np.abs(L - L.conj().T).max() < 1e-9 * np.abs(L).max()
+    # without the Nyquist reading the symmetry is lost (even axes present)
+    assert any(s % 2 == 0 for s in shape)
+
+
+def test_curl_curl_fft_matches_dense():
+    g = small_grid((4, 5, 6), pml=(0, 0, 0))
+    E = scenes.random_field((4, 5, 6), 7).astype(np.complex128)
+    L = dense.curl_curl_dense(g)
+    ref = (L @ E.reshape(-1)).reshape(E.shape)
+    assert rel(oc.curl_curl_apply(g, E), ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# CBS reaches the plain definition (dense LU)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,pml,loss,seed", [
+    ((4, 5, 6), (1, 1, 1), 0.0, 1),
+    ((5, 5, 5), (1, 1, 2), 0.3, 2),
+    ((6, 4, 7), (0, 1, 2), 0.0, 3),
+    ((8, 8, 8), (2, 2, 2), 0.1, 4),
+])
+def test_cbs_converges_to_dense_solution(shape, pml, loss, seed):
+    """CBS reaches A^-1 S on every voxel where gamma != 0.  Where the absorbing
+    potential sits exactly on the shift's bound (V0 = i eps, so V = 0 and
+    gamma = 0) the iteration never updates the voxel, which keeps E^(0) = 0;
+    because V = 0 there, such voxels feed nothing back into the rest."""
+    g = small_grid(shape, pml=pml)
+    eps = scenes.random_passive_eps(shape, pml, seed, loss=loss)
+    S = oc.plane_wave_source(g, eps)
+    ref = dense.dense_solve(g, eps, S)
+    res = oc.cbs(g, eps, S, tol=1e-14, max_iter=20000)
+    assert res.eta <= 1e-14
+    pot = oc.potentials(g, eps)
+    stuck = np.abs(pot.gamma) < 1e-12
+    assert not np.any(stuck & oc.interior_mask(g))
+    live = np.broadcast_to(~stuck, res.E_s.shape)
+    assert rel(res.E_s[live], ref[live]) < 1e-9
+    assert np.all(res.E_s[~live] == 0)
+
+
+@pytest.mark.parametrize("shape,pml,seed", [((5, 5, 5), (1, 1, 2), 2), ((6, 5, 4), (1, 2, 1), 6)])
+def test_cbs_weak_layer_matches_dense_everywhere(shape, pml, seed):
+    """With sigma_max below the scatterer's contrast no voxel is degenerate and
+    the whole field equals A^-1 S."""
+    g = small_grid(shape, pml=pml, sigma_max=0.5)
+    eps = scenes.random_passive_eps(shape, pml, seed, lo=1.6, hi=2.1, loss=0.2)
+    assert np.abs(oc.potentials(g, eps).gamma).min() > 0.1
+    S = oc.plane_wave_source(g, eps)
+    res = oc.cbs(g, eps, S, tol=1e-14, max_iter=20000)
+    assert rel(res.E_s, dense.dense_solve(g, eps, S)) < 1e-9
+
+
+def test_cbs_point_source_converges_to_dense():
+    g = small_grid((5, 6, 7), pml=(1, 1, 1))
+    eps = scenes.random_passive_eps((5, 6, 7), (1, 1, 1), 9, loss=0.2)
+    S = oc.point_source(g, (2, 3, 3), [1.0, 0.5j, -0.25])
+    ref = dense.dense_solve(g, eps, S)
+    res = oc.cbs(g, eps, S, tol=1e-14, max_iter=20000)
+    assert rel(res.E_s, ref) < 1e-9
+
+
+def test_gmres_matches_dense():
+    g = small_grid((4, 5, 6), pml=(1, 1, 1))
+    eps = scenes.random_passive_eps((4, 5, 6), (1, 1, 1), 5, loss=0.1)
+    S = oc.plane_wave_source(g, eps)
+    assert rel(dense.gmres_solve(g, eps, S, rtol=1e-13), dense.dense_solve(g, eps, S)) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Uniform medium: per-mode closed form of every iterate
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(6, 5, 4), (9, 8, 7)])
+def test_uniform_medium_iterates_closed_form(shape):
+    g = small_grid(shape, pml=(0, 0, 0))
+    eps_c = complex(np.complex64(1.3 + 0.05j))   # the value the solver sees
+    eps = np.full(g.vshape, eps_c, dtype=np.complex64)
+    S = scenes.random_field(shape, 11).astype(np.complex128)
+    for k in (1, 4, 25):
+        Ek, _ = closed.uniform_medium(g, eps_c, S, k)
+        res = oc.cbs(g, eps, S, tol=0.0, max_iter=k)
+        assert res.iterations == k
+        assert rel(res.E_s, Ek) < 1e-12
+    # the converged per-mode solution is A^-1 S of the dense system (in a
+    # uniform medium |1 - gamma| = |V0|/eps = 1, so high-|p| modes converge
+    # too slowly for the iteration itself to be run to 1e-10 here)
+    _, Einf = closed.uniform_medium(g, eps_c, S, 0)
+    assert rel(Einf, dense.dense_solve(g, eps, S)) < 1e-10
+
+
+def test_uniform_plane_wave_source_closed_form():
+    g = small_grid((4, 4, 12), pml=(0, 0, 0))
+    eps_c = 1.7 + 0.02j
+    eps = np.full(g.vshape, eps_c, dtype=np.complex64)
+    S = oc.plane_wave_source(g, eps)
+    Ek, Einf = closed.uniform_medium(g, complex(np.complex64(eps_c)), S, 10)
+    assert rel(oc.cbs(g, eps, S, tol=0.0, max_iter=10).E_s, Ek) < 1e-12
+    assert rel(Einf, dense.dense_solve(g, eps, S)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Special cases and invariants
+# ---------------------------------------------------------------------------
+def test_homogeneous_medium_reproduces_incident_wave_exactly():
+    g = small_grid((6, 6, 10), pml=(2, 2, 3))
+    eps = np.ones(g.vshape, dtype=np.float32)
+    E, res = oc.solve_forward(g, eps, tol=0.0, max_iter=15)
+    assert np.all(res.E_s == 0)
+    assert np.array_equal(E, oc.plane_wave(g))
+
+
+def test_converged_field_is_shift_independent():
+    g = small_grid((5, 6, 7), pml=(1, 1, 2))
+    eps = scenes.random_passive_eps((5, 6, 7), (1, 1, 2), 12)
+    S = oc.plane_wave_source(g, eps)
+    r1 = oc.cbs(g, eps, S, tol=1e-14, max_iter=40000)
+    r2 = oc.cbs(g, eps, S, tol=1e-14, max_iter=40000, eps_shift=2.0 * r1.eps)
+    assert rel(r1.E_s, r2.E_s) < 1e-10
+
+
+def test_reciprocity():
+    g = small_grid((6, 5, 7), pml=(1, 1, 2))
+    eps = scenes.random_passive_eps((6, 5, 7), (1, 1, 2), 13, loss=0.1)
+    r1, r2 = (1, 2, 2), (4, 2, 5)
+    a = np.array([1.0, -0.3, 0.2j])
+    b = np.array([0.1, 0.7, -0.5])
+    E1 = oc.cbs(g, eps, oc.point_source(g, r1, a), tol=1e-14, max_iter=40000).E_s
+    E2 = oc.cbs(g, eps, oc.point_source(g, r2, b), tol=1e-14, max_iter=40000).E_s
+    lhs = np.dot(b, E1[:, r2[2], r2[1], r2[0]])
+    rhs = np.dot(a, E2[:, r1[2], r1[1], r1[0]])
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+
+
+def test_energy_balance():
+    g = small_grid((6, 6, 8), pml=(1, 1, 2))
+    eps = scenes.random_passive_eps((6, 6, 8), (1, 1, 2), 14, loss=0.2)
+    S = oc.plane_wave_source(g, eps)
+    Es = oc.cbs(g, eps, S, tol=1e-14, max_iter=40000).E_s
+    K = oc.potentials(g, eps).K
+    absorbed = float(np.sum(K.imag[None] * np.abs(Es) ** 2))
+    delivered = float(np.imag(np.vdot(Es, S)))
+    assert abs(absorbed + delivered) < 1e-9 * abs(absorbed)
+
+
+def test_mirror_symmetry_of_sphere_scattering():
+    sc = scenes.sphere_scene(16, LAM / 6, 0.6e-6, 1.45, 1.0, (3, 3, 3), supersample=4)
+    g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
+    # every iterate carries the symmetry, so a fixed iteration count suffices
+    E, _ = oc.solve_forward(g, sc.eps_r, tol=0.0, max_iter=120)
+    Ex, Ey, Ez = E
+    fx = lambda a: a[:, :, ::-1]   # x -> nx-1-x
+    fy = lambda a: a[:, ::-1, :]
+    s = np.abs(E).max()
+    assert np.abs(fx(Ex) - Ex).max() < 1e-9 * s and np.abs(fy(Ex) - Ex).max() < 1e-9 * s
+    assert np.abs(fx(Ey) + Ey).max() < 1e-9 * s and np.abs(fy(Ey) + Ey).max() < 1e-9 * s
+    assert np.abs(fx(Ez) + Ez).max() < 1e-9 * s and np.abs(fy(Ez) - Ez).max() < 1e-9 * s
+    assert np.abs(Ey).max() > 1e-4 * s and np.abs(Ez).max() > 1e-3 * s   # not trivially zero
+
+
+def test_slab_reduces_to_1d_scalar_helmholtz():
+    nz, pz = 48, 10
+    g = oc.Grid(3, 4, nz, LAM / 8, LAM, 1.0, (0, 0, pz))
+    eps = np.ones(g.vshape, dtype=np.complex64)
+    eps_z = np.ones(nz, dtype=np.complex64)
+    eps_z[18:27] = 2.1025
+    eps_z[27:30] = 1.5 + 0.1j
+    eps[:] = eps_z[:, None, None]
+    S = oc.plane_wave_source(g, eps)
+    Es = oc.cbs(g, eps, S, tol=1e-14, max_iter=40000).E_s
+    ref = closed.slab_1d(nz, g.pitch, LAM, 1.0, pz, eps_z, S[0, :, 0, 0])
+    assert rel(Es[0, :, 1, 2], ref) < 1e-10
+    assert np.abs(Es[1:]).max() < 1e-12 * np.abs(Es[0]).max()
+    assert np.abs(Es[0] - Es[0, :, :1, :1]).max() < 1e-10 * np.abs(Es[0]).max()
+
+
+def test_slab_transmission_matches_fabry_perot():
+    """Continuum check (discretisation-limited): a lossless slab of index n and
+    thickness L in vacuum transmits t = 1/(cos(nkL) - i (n + 1/n)/2 sin(nkL))
+    times exp(i k L) relative to the incident wave; the spectral discretisation
+    at lambda/32 with a thick absorbing layer reproduces it to ~1e-2."""
+    d = LAM / 32
+    pz = 6 * 32
+    n_core = 64
+    nz = 2 * pz + 2 * 48 + n_core
+    z0 = pz + 48
+    n = 1.45
+    eps_z = np.ones(nz, dtype=np.complex64)
+    eps_z[z0:z0 + n_core] = n * n
+    k = 2 * math.pi / LAM
+    Lz = n_core * d
+    # incident + scattered in 1D
+    S = k ** 2 * (eps_z.astype(np.complex128) - 1) * np.exp(1j * k * np.arange(nz) * d)
+    e = closed.slab_1d(nz, d, LAM, 1.0, pz, eps_z, S)
+    E = np.exp(1j * k * np.arange(nz) * d) + e
+    # slab faces sit half a voxel outside the first/last filled voxel centres
+    zt = z0 + n_core + 24
+    t = 1.0 / (math.cos(n * k * Lz) - 0.5j * (n + 1 / n) * math.sin(n * k * Lz))
+    # beyond the slab E(z) = t exp(i k (z - L)): the ratio to the incident
+    # wave is t exp(-i k L), independent of where the slab sits
+    ratio = E[zt] / np.exp(1j * k * zt * d)
+    assert abs(ratio - t * np.exp(-1j * k * Lz)) < 2e-2
+    assert abs(abs(E[zt]) - abs(t)) < 1e-2
+
+
+# ---------------------------------------------------------------------------
+# Adjoint gradient vs FP64 central finite differences
+# ---------------------------------------------------------------------------
+def test_adjoint_gradient_matches_central_differences():
+    shape, pml = (8, 8, 10), (1, 1, 2)
+    g = small_grid(shape, pml=pml)
+    eps = scenes.random_passive_eps(shape, pml, 21).astype(np.float64)
+    r0 = (4, 4, 7)
+    L0, res = oc.objective_of_eps(g, eps, r0, 1e-14, 40000)
+    E = oc.plane_wave(g) + res.E_s
+    adj = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, E, r0), tol=1e-14, max_iter=40000)
+    grad = oc.gradient(g, E, adj.E_s)
+    rng = np.random.default_rng(1)
+    h = 1e-4
+    for _ in range(6):
+        v = (rng.integers(1, 7), rng.integers(1, 7), rng.integers(2, 8))
+        ep, em = eps.copy(), eps.copy()
+        ep[v[2], v[1], v[0]] += h
+        em[v[2], v[1], v[0]] -= h
+        Lp, _ = oc.objective_of_eps(g, ep, r0, 1e-14, 40000, res.E_s)
+        Lm, _ = oc.objective_of_eps(g, em, r0, 1e-14, 40000, res.E_s)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(grad[v[2], v[1], v[0]] - fd) <= 1e-6 * max(abs(fd), 1e-3 * L0)
+
+
+# ---------------------------------------------------------------------------
+# Scene geometry vs the numbers the paper prints
+# ---------------------------------------------------------------------------
+def test_scene_geometry_matches_paper():
+    gold = json.load(open(os.path.join(GOLDEN, "paper_geometry.json")))
+    f4 = gold["fig4_volume"]
+    ext = [n * f4["pitch_m"] * 1e6 for n in f4["grid"]]
+    assert all(abs(e - x) / x < 0.01 for e, x in zip(ext, f4["extent_um"]))
+    f3 = gold["fig3_volume"]
+    assert abs(np.prod(f3["grid"]) / 1e6 - f3["megavoxels"]) < 0.05
+    ext3 = [n * f3["pitch_m"] * 1e6 for n in f3["grid"]]
+    assert all(abs(e - x) / x < 0.03 for e, x in zip(ext3, f3["extent_um"]))
+    f1 = gold["fig1_lens"]
+    f = scenes.focal_length(f1["D_m"], f1["NA"])
+    assert math.isclose(math.asin(f1["NA"]), math.atan(f1["D_m"] / (2 * f)), rel_tol=1e-12)
+    # absorbing layer [1, 1, 6] lambda read as totals per axis, split per side
+    pitch = gold["wavelength_m"]["value"] / f1["pitch_over_lambda"]
+    assert scenes.pml_voxels(pitch) == (8, 8, 48)
+    assert scenes.pml_voxels(177e-9) == (8, 8, 18)
+
+
+def test_zone_plate_focus_and_slab():
+    sc = scenes.zoneplate16()
+    assert sc.shape == (275, 275, 315) and sc.r0 == (137, 137, 151)
+    assert sc.info["z_base"] == 56 and sc.info["zones"] == 8
+    e = sc.eps_r
+    assert e.max() <= np.float32(1.45 ** 2) and e.min() == 1.0
+    assert np.array_equal(e, e[:, ::-1, :]) and np.array_equal(e, e[:, :, ::-1])
+    d = scenes.design_slab(sc)
+    lo, hi = d.design_box
+    assert int(np.prod([b - a for a, b in zip(lo, hi)])) == 2012430
+    assert d.eps_r.min() >= 1.0 and d.eps_r.max() <= np.float32(2.1)
