@@ -1,0 +1,187 @@
+/*
+ * cbs.h -- C ABI of the MI355X (gfx950) vector convergent Born series solver.
+ *
+ * The library solves the 3D vector Helmholtz (Maxwell) problem of arXiv
+ * 2506.15411 (simulation-setup paragraph: CBS of its references [25] and [26],
+ * absorbing layer of reference [31]; design paragraph: x-polarised plane wave
+ * at normal incidence) and the adjoint problem used for its permittivity
+ * gradient (objective and optimisation paragraphs, Fig. 2):
+ *
+ *     (L - K) E_s = S,   L = F^-1 diag(|p|^2 I - pt pt^T) F,
+ *     K = k0^2 eps_r + i kb^2 sigma,  kb = k0 n_bg,
+ *
+ * by the iteration  E_s <- E_s + gamma [G (V E_s + S) - E_s]  with
+ * V = K - kb^2 - i eps, gamma = (i/eps) V, eps = kappa max|K - kb^2| (kappa >= 1,
+ * the convergence condition of reference [25] being eps >= max|K - kb^2|) and
+ * G^(p) = (|p|^2 I - pt pt^T - (kb^2 + i eps) I)^-1 applied by FFT.
+ * pt equals p except at the Nyquist bin of an even axis, where it is 0.
+ *
+ * Conventions shared by every entry point
+ *   - time dependence exp(-i w t); Im eps_r >= 0 (passive media only);
+ *   - a grid of nx * ny * nz voxels with one pitch d; voxel (i, j, k) is
+ *     centred at (i d, j d, k d);
+ *   - scalar volumes are [nz][ny][nx] (x fastest); vector fields are
+ *     complex64 (interleaved re, im) [3][nz][ny][nx], component 0 = x;
+ *   - every pointer named *_dev is device memory (HBM) owned by the caller
+ *     and borrowed for the duration of the call; the library never allocates
+ *     device memory: all scratch lives in the caller's workspace;
+ *   - all work is ordered on the HIP stream given at plan creation;
+ *   - functions return a cbs_status; cbs_last_error() describes the last
+ *     non-OK status of the calling thread.
+ *   - a plan is used by one host thread at a time; distinct plans (with
+ *     distinct workspaces) may run concurrently.
+ */
+#ifndef CBS_H
+#define CBS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cbs_plan_s* cbs_plan_t;
+
+typedef enum {
+  CBS_OK = 0,
+  CBS_NOT_CONVERGED = 1,   /* max_iter reached; the output holds the last iterate */
+  CBS_E_INVALID = -1,      /* bad argument, inadmissible medium, unsupported size  */
+  CBS_E_WORKSPACE = -2,    /* workspace missing, misaligned or too small          */
+  CBS_E_HIP = -3,          /* a HIP runtime call failed                            */
+  CBS_E_DIVERGED = -4,     /* non-finite residual                                  */
+  CBS_E_STATE = -5         /* call out of order (e.g. solve before permittivity)   */
+} cbs_status;
+
+enum { CBS_F32 = 0, CBS_C64 = 1 };   /* permittivity dtype */
+
+enum {
+  CBS_SRC_NONE = 0,        /* S = 0 */
+  CBS_SRC_PLANE_WAVE = 1,  /* S = k0^2 (eps_r - n_bg^2) pol exp(i kb z), +z incidence  */
+  CBS_SRC_FIELD = 2,       /* S = field (device complex64 [3][nz][ny][nx], units 1/m^2) */
+  CBS_SRC_POINT = 3        /* S = amp at voxel r0, zero elsewhere (units 1/m^2)        */
+};
+
+enum {
+  CBS_WARM_START = 1u,        /* E_dev holds the initial iterate (total field for a
+                                 plane-wave solve, adjoint field for an adjoint solve) */
+  CBS_RETURN_SCATTERED = 2u,  /* plane-wave solve: return E_s instead of E_inc + E_s */
+  CBS_RECORD_HISTORY = 4u     /* keep the residual of every iteration (cbs_history) */
+};
+
+typedef struct {
+  double tol;          /* stop when ||E^(k+1) - E^(k)|| / ||E^(k+1)|| <= tol (FP64 norms) */
+  int max_iter;        /* hard cap on iterations (>= 1)                                   */
+  int check_every;     /* host polls the device convergence flag every this many
+                          iterations (>= 1); iterations past convergence are skipped on
+                          the device, so this only trades host syncs for idle launches   */
+  unsigned flags;      /* CBS_WARM_START | CBS_RETURN_SCATTERED | CBS_RECORD_HISTORY      */
+} cbs_opts;
+
+typedef struct {
+  int iterations;      /* updates applied                                  */
+  int converged;       /* 1 if the residual reached tol                    */
+  double residual;     /* last relative update norm (FP64)                 */
+  double eps_shift;    /* eps in 1/m^2                                     */
+  float ms;            /* device time of the iteration loop (HIP events)   */
+} cbs_stats;
+
+typedef struct {
+  int kind;                 /* CBS_SRC_*                                              */
+  double pol[3][2];         /* PLANE_WAVE: polarisation (re, im) per component;
+                               all zero means x-polarised                             */
+  const void* field;        /* FIELD: device complex64 [3][nz][ny][nx]                */
+  int r0[3];                /* POINT: voxel (ix, iy, iz)                              */
+  double amp[3][2];         /* POINT: amplitude (re, im) per component                */
+} cbs_source;
+
+/* Device bytes a plan of this grid needs as workspace (exact). 0 if the grid
+ * is not supported (see cbs_axis_supported). */
+size_t cbs_plan_workspace_bytes(int nx, int ny, int nz);
+
+/* 1 if n is a supported length for axis 0 = x, 1 = y, 2 = z, else 0.
+ * The FFT passes are specialised per length (two-level splits n = n1 * n2
+ * with register codelets for radices 2..37). */
+int cbs_axis_supported(int axis, int n);
+
+/* Create a plan.
+ *   nx, ny, nz     grid (each >= 2 and supported on its axis)
+ *   pitch_m        voxel pitch d > 0 (metres)
+ *   lambda0_m      vacuum wavelength > 0 (metres)
+ *   n_bg           background index > 0 (real)
+ *   pml            per-side absorbing-layer thickness in voxels, 0 <= 2 pml[a] < n[a]
+ *   workspace_dev  caller device memory, >= cbs_plan_workspace_bytes, 256-byte aligned,
+ *                  must outlive the plan
+ *   stream         hipStream_t the plan's work is ordered on (NULL = default stream)
+ * The absorbing profile defaults to sigma = 1 * min(1, sum_a u_a^2), u_a the depth
+ * into the layer in units of its thickness (outermost voxel u = 1). */
+int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m,
+                    double lambda0_m, double n_bg, const int pml[3],
+                    void* workspace_dev, size_t workspace_bytes, void* stream);
+
+/* Change the absorbing profile: sigma = sigma_max * min(1, sum_a u_a^order).
+ * Must precede cbs_set_permittivity (it invalidates the potential). */
+int cbs_plan_set_pml_profile(cbs_plan_t plan, int order, double sigma_max);
+
+/* Set eps = kappa * max|K - kb^2| (kappa >= 1, default 1.1).  Every admissible
+ * eps gives the same converged field; kappa slightly above 1 damps the high
+ * spatial frequencies of the strongest-contrast voxels, which kappa = 1 leaves
+ * undamped (local factor |V0|/eps = 1).  Must precede cbs_set_permittivity. */
+int cbs_plan_set_shift_factor(cbs_plan_t plan, double kappa);
+
+/* Set the medium: eps_r_dev is [nz][ny][nx] float32 (CBS_F32) or complex64
+ * (CBS_C64).  Validates finiteness, Im eps_r >= 0 and eps_r == n_bg^2 (at
+ * float32) inside the absorbing layer, builds the potential on the device and
+ * computes eps = kappa max|K - kb^2| with the maximum taken in FP64 (floor
+ * 1e-3 kb^2 on the maximum).  Synchronises the stream. */
+int cbs_set_permittivity(cbs_plan_t plan, const void* eps_r_dev, int dtype);
+
+/* Forward solve.  src = NULL means an x-polarised plane wave.  E_dev is
+ * complex64 [3][nz][ny][nx]: on return the total field E_inc + E_s for a
+ * plane-wave source (E_s with CBS_RETURN_SCATTERED), or the solution of
+ * A E = S for FIELD/POINT/NONE sources.  Synchronises the stream.
+ * Returns CBS_OK, CBS_NOT_CONVERGED (valid last iterate) or an error. */
+int cbs_solve(cbs_plan_t plan, const cbs_source* src, void* E_dev,
+              const cbs_opts* opts, cbs_stats* stats);
+
+/* Adjoint solve with the same operator (A is complex-symmetric, so the
+ * adjoint field of a real objective is E_adj = A^-1 g with g the conjugated
+ * derivative of the objective).
+ *   adj_src POINT with E_fwd_dev != NULL: g = conj(E_fwd(r0)) at r0, built on
+ *           the device (gradient of |E(r0)|^2 with scale 2 in cbs_gradient);
+ *   adj_src POINT with E_fwd_dev == NULL: g = adj_src->amp at r0;
+ *   adj_src FIELD: g = adj_src->field.
+ * E_adj_dev receives complex64 [3][nz][ny][nx].  Synchronises the stream. */
+int cbs_adjoint_solve(cbs_plan_t plan, const void* E_fwd_dev, const cbs_source* adj_src,
+                      void* E_adj_dev, const cbs_opts* opts, cbs_stats* stats);
+
+/* Permittivity gradient over a half-open box [lo, hi) (x, y, z):
+ *   grad[z][y][x] = scale * k0^2 * Re(sum_c E_adj,c * E_c)
+ * (dK/d eps_r = k0^2; scale = 2 for the adjoint source conj(E(r0)) of
+ * |E(r0)|^2, 1 for a source conj(gE) with gE = 2 dL/dE*).  grad_dev is float32,
+ * box-shaped, x fastest.  Asynchronous on the plan's stream. */
+int cbs_gradient(cbs_plan_t plan, const void* E_dev, const void* E_adj_dev,
+                 const int box_lo[3], const int box_hi[3], double scale, float* grad_dev);
+
+/* One application of the Green's operator of the current medium:
+ * out = F^-1 G^(p) F in  (complex64 fields; in and out may not alias).
+ * Asynchronous on the plan's stream. */
+int cbs_apply_green(cbs_plan_t plan, const void* in_dev, void* out_dev);
+
+/* Residual history of the last solve with CBS_RECORD_HISTORY: copies up to
+ * max entries into host memory, returns the number available (>= 0) or an
+ * error. */
+int cbs_history(cbs_plan_t plan, double* out_host, int max);
+
+/* eps (1/m^2) of the current medium, or a negative value if none is set. */
+double cbs_eps_shift(cbs_plan_t plan);
+
+int cbs_plan_destroy(cbs_plan_t plan);
+
+/* Message describing the last non-OK status returned on this thread. */
+const char* cbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CBS_H */

@@ -11,15 +11,20 @@ The paper prints none of the CBS equations; this module restates them:
 
     A E_s = S,  A = L - K I_3,  L = F^-1 diag(M(p)) F,  M(p) = |p|^2 I - pt pt^T
     K(r)  = k0^2 eps_r(r) + i kb^2 sigma(r)          (sigma: absorbing profile)
-    V0    = K - kb^2,  eps = max|V0|,  V = V0 - i eps,  gamma = (i/eps) V
+    V0    = K - kb^2,  eps = kappa max|V0|,  V = V0 - i eps,  gamma = (i/eps) V
     G^(p) = (M(p) - (kb^2 + i eps) I)^-1                (dyadic Green's tensor)
     iteration:  E_s <- E_s + gamma (F^-1 G^ F (V E_s + S) - E_s),  E_s^(0) = 0
 
 Readings taken where the paper is silent (each also listed in the design notes):
   * time convention exp(-i w t); Im eps_r >= 0 is passive/absorbing;
-  * eps = max|V0| over the grid with a floor of 1e-3 kb^2 (the [25] condition
-    is on the unshifted potential; "eps >= max|V|" with the shifted V is
-    impossible since |V0 - i eps| >= eps);
+  * eps = kappa * max|V0| over the grid (floor 1e-3 kb^2 on max|V0|), with
+    kappa >= 1 (default 1.1).  The convergence condition of [25] is on the
+    unshifted potential, eps >= max|V0| ("eps >= max|V|" with the shifted V is
+    impossible since |V0 - i eps| >= eps).  Any admissible eps gives the same
+    converged field; kappa = 1 leaves the local factor |1 - gamma| = |V0|/eps
+    at 1 in the strongest-contrast voxels, where high spatial frequencies then
+    barely decay, and makes gamma = 0 (voxels never updated) wherever the
+    absorbing potential alone attains the bound;
   * Nyquist bins of even axes: pt (the vector in the dyadic term only) is zero
     there, which makes A exactly complex-symmetric (A^T = A);
   * scattered-field formulation: S = k0^2 (eps_r - n_bg^2) E_inc with
@@ -68,6 +73,7 @@ class Grid:
     pml: tuple = (0, 0, 0)
     pml_order: int = 2
     sigma_max: float = 1.0
+    shift_factor: float = 1.1
 
     @property
     def k0(self) -> float:
@@ -150,14 +156,15 @@ def validate(g: Grid, eps_r: np.ndarray) -> None:
 class Potentials:
     K: np.ndarray        # k0^2 eps_r + i kb^2 sigma           [nz,ny,nx] complex128
     V0: np.ndarray       # K - kb^2                             unshifted potential
-    eps: float           # shift, max|V0| (floor 1e-3 kb^2)
+    eps: float           # shift, kappa * max|V0| (floor 1e-3 kb^2)
     V: np.ndarray        # V0 - i eps                           shifted potential
     gamma: np.ndarray    # (i/eps) V = 1 + i V0/eps             preconditioner
     kt2: complex         # kb^2 + i eps                         Green's denominator
 
 
 def potentials(g: Grid, eps_r: np.ndarray, eps_shift: float | None = None) -> Potentials:
-    """K, V0, eps, V, gamma exactly as defined for CBS in [25]/[26].
+    """K, V0, eps, V, gamma exactly as defined for CBS in [25]/[26]
+    (eps = shift_factor * max|V0|, see the module notes).
 
     V0 is formed as k0^2 (eps_r - n_bg^2) + i kb^2 sigma, which equals
     K - kb^2 without the cancellation of subtracting two large numbers.
@@ -170,7 +177,7 @@ def potentials(g: Grid, eps_r: np.ndarray, eps_shift: float | None = None) -> Po
     V0 = k0sq * (eps_r - g.n_bg ** 2) + 1j * kb2 * sigma
     K = V0 + kb2
     if eps_shift is None:
-        eps = max(float(np.max(np.abs(V0))) if V0.size else 0.0, 1e-3 * kb2)
+        eps = g.shift_factor * max(float(np.max(np.abs(V0))) if V0.size else 0.0, 1e-3 * kb2)
     else:
         eps = float(eps_shift)
     V = V0 - 1j * eps

@@ -51,7 +51,7 @@ def uniform_medium(g, eps_const: complex, S: np.ndarray, iterations: int):
     k0sq = g.k0 ** 2
     kb2 = g.kb ** 2
     V0 = k0sq * (complex(eps_const) - g.n_bg ** 2)
-    eps = max(abs(V0), 1e-3 * kb2)
+    eps = g.shift_factor * max(abs(V0), 1e-3 * kb2)
     V = V0 - 1j * eps
     gamma = 1j * V / eps
     kt2 = kb2 + 1j * eps

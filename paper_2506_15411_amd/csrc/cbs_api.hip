@@ -1,0 +1,804 @@
+// C ABI of the CBS solver: plans, setup kernels, the iteration loop,
+// adjoint source, gradient and the Green's-operator entry point.
+//
+// The operation each entry point performs is specified in include/cbs.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cbs.h"
+#include "kernels.hpp"
+
+namespace cbs {
+
+const SizeOps* sizes_small(int* count);
+const SizeOps* sizes_mid(int* count);
+const SizeOps* sizes_large(int* count);
+
+const SizeOps* find_size(int n) {
+  const SizeOps* (*tables[])(int*) = {sizes_small, sizes_mid, sizes_large};
+  for (auto tab : tables) {
+    int cnt = 0;
+    const SizeOps* t = tab(&cnt);
+    for (int i = 0; i < cnt; ++i)
+      if (t[i].n == n) return &t[i];
+  }
+  return nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess) return fail(CBS_E_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define HIP_LAUNCHED()                                                              \
+  do {                                                                              \
+    hipError_t e_ = hipGetLastError();                                              \
+    if (e_ != hipSuccess) return fail(CBS_E_HIP, "kernel launch: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// setup and small kernels
+// ---------------------------------------------------------------------------
+constexpr int kSetupBlocks = 1024;
+constexpr int kSetupThreads = 256;
+
+struct SetupArgs {
+  int nx, ny, nz, px, py, pz, order, dtype;
+  double sigma_max, k0d2, kbd2, nb2;
+  float nb2f;
+  const void* eps;
+  float2* V0;
+  double* part;  // 2 per block: max|V0|, flags
+};
+
+__device__ __forceinline__ double layer_depth(int i, int n, int p) {
+  if (p <= 0) return 0.0;
+  if (i < p) return double(p - i) / double(p);
+  if (i >= n - p) return double(i - (n - p - 1)) / double(p);
+  return 0.0;
+}
+
+__device__ __forceinline__ double ipow(double u, int m) {
+  double r = 1.0;
+  for (int k = 0; k < m; ++k) r *= u;
+  return r;
+}
+
+// sigma, V0 = k0^2 (eps_r - n_bg^2) + i kb^2 sigma (times d^2), max|V0| in
+// FP64 and input validation flags (1 non-finite, 2 gain, 4 layer != n_bg^2)
+__global__ void __launch_bounds__(kSetupThreads) k_setup(SetupArgs a) {
+  __shared__ double smx[kSetupThreads / 64];
+  __shared__ unsigned sfl[kSetupThreads / 64];
+  const long long N = (long long)a.nx * a.ny * a.nz;
+  double mx = 0.0;
+  unsigned fl = 0;
+  for (long long i = (long long)blockIdx.x * kSetupThreads + threadIdx.x; i < N;
+       i += (long long)gridDim.x * kSetupThreads) {
+    const int x = (int)(i % a.nx);
+    const long long r = i / a.nx;
+    const int y = (int)(r % a.ny);
+    const int z = (int)(r / a.ny);
+    float er, ei;
+    if (a.dtype == CBS_F32) {
+      er = static_cast<const float*>(a.eps)[i];
+      ei = 0.f;
+    } else {
+      const float2 e = static_cast<const float2*>(a.eps)[i];
+      er = e.x;
+      ei = e.y;
+    }
+    if (!isfinite(er) || !isfinite(ei)) fl |= 1u;
+    if (ei < 0.f) fl |= 2u;
+    const bool layer = x < a.px || x >= a.nx - a.px || y < a.py || y >= a.ny - a.py ||
+                       z < a.pz || z >= a.nz - a.pz;
+    if (layer && (er != a.nb2f || ei != 0.f)) fl |= 4u;
+    const double su = ipow(layer_depth(x, a.nx, a.px), a.order) +
+                      ipow(layer_depth(y, a.ny, a.py), a.order) +
+                      ipow(layer_depth(z, a.nz, a.pz), a.order);
+    const double sigma = a.sigma_max * (su < 1.0 ? su : 1.0);
+    const double vr = a.k0d2 * ((double)er - a.nb2);
+    const double vi = a.k0d2 * (double)ei + a.kbd2 * sigma;
+    const double m = sqrt(vr * vr + vi * vi);
+    mx = m > mx ? m : mx;
+    a.V0[i] = make_float2((float)vr, (float)vi);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const double om = __shfl_xor(mx, o, 64);
+    mx = om > mx ? om : mx;
+    fl |= (unsigned)__shfl_xor((int)fl, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    smx[wv] = mx;
+    sfl[wv] = fl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kSetupThreads / 64; ++w) {
+      mx = smx[w] > smx[0] ? smx[w] : smx[0];
+      smx[0] = mx;
+      sfl[0] |= sfl[w];
+    }
+    a.part[2 * blockIdx.x] = smx[0];
+    a.part[2 * blockIdx.x + 1] = (double)sfl[0];
+  }
+}
+
+__global__ void k_state_init(DevState* st, double tol, int max_iter, int record) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->done = 0;
+    st->iter = 0;
+    st->status = 0;
+    st->max_iter = max_iter;
+    st->tol = tol;
+    st->eta = INFINITY;
+    st->record = record;
+  }
+}
+
+// point-source amplitude: conj(E(r0)) * scale (from_field) or given * scale
+__global__ void k_point_amp(DevState* st, const float2* E, long long idx, long long sE,
+                            int from_field, float scale, float2 g0, float2 g1, float2 g2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (from_field) {
+      for (int c = 0; c < 3; ++c) {
+        const float2 e = E[c * sE + idx];
+        st->amp[c] = make_float2(e.x * scale, -e.y * scale);
+      }
+    } else {
+      st->amp[0] = make_float2(g0.x * scale, g0.y * scale);
+      st->amp[1] = make_float2(g1.x * scale, g1.y * scale);
+      st->amp[2] = make_float2(g2.x * scale, g2.y * scale);
+    }
+  }
+}
+
+// eta = sqrt(sum |dE|^2 / sum |E|^2) over the K1 block partials (fixed order)
+constexpr int kResThreads = 256;
+__global__ void __launch_bounds__(kResThreads)
+k_residual(const double* part, int nb, DevState* st, double* hist) {
+  __shared__ double s0[kResThreads], s1[kResThreads];
+  if (st->done) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kResThreads) {
+    a += part[2 * i];
+    b += part[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = kResThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nd = s0[0], ne = s1[0];
+    double eta;
+    if (ne > 0.0)
+      eta = sqrt(nd / ne);
+    else
+      eta = (nd == 0.0) ? 0.0 : INFINITY;
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->eta = eta;
+    if (st->record && it <= kHistCap) hist[it - 1] = eta;
+    if (!isfinite(eta)) {
+      st->status = 3;
+      st->done = 1;
+    } else if (eta <= st->tol) {
+      st->status = 1;
+      st->done = 1;
+    } else if (it >= st->max_iter) {
+      st->status = 2;
+      st->done = 1;
+    }
+  }
+}
+
+// E += sign * pol exp(i kb z)  (incident field)
+__global__ void k_incident(float2* E, const float2* phase, int nx, int ny, int nz, float2 p0,
+                           float2 p1, float2 p2, float sign) {
+  const long long N = (long long)nx * ny * nz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int z = (int)(i / ((long long)nx * ny));
+    const float2 ph = phase[z];
+    const float2 pc[3] = {p0, p1, p2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float2 inc = cmul(ph, pc[c]);
+      float2 e = E[c * N + i];
+      e.x += sign * inc.x;
+      e.y += sign * inc.y;
+      E[c * N + i] = e;
+    }
+  }
+}
+
+// grad[z][y][x] = scale * Re(sum_c Ea_c E_c) over the box (FP64 accumulate)
+__global__ void k_gradient(const float2* E, const float2* Ea, long long sE, int nx, int ny,
+                           int x0, int y0, int z0, int bx, int by, int bz, double scale,
+                           float* grad) {
+  const long long NB = (long long)bx * by * bz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NB;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int xi = (int)(i % bx);
+    const long long r = i / bx;
+    const int yi = (int)(r % by);
+    const int zi = (int)(r / by);
+    const long long idx = ((long long)(z0 + zi) * ny + (y0 + yi)) * nx + (x0 + xi);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float2 e = E[c * sE + idx], ea = Ea[c * sE + idx];
+      s += (double)ea.x * (double)e.x - (double)ea.y * (double)e.y;
+    }
+    grad[i] = (float)(scale * s);
+  }
+}
+
+}  // namespace cbs
+
+using namespace cbs;
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+struct cbs_plan_s {
+  int nx, ny, nz, nxp;
+  int pml[3];
+  double pitch, lambda0, n_bg, k0, kb;
+  int order;
+  double sigma_max;
+  double shift_factor;
+  const SizeOps *ox, *oy, *oz;
+  int k1_blocks;
+  hipStream_t stream;
+  // workspace carve-up
+  float2 *W, *V0, *twx, *twy, *twz, *phase;
+  double *partials, *setup_part, *hist;
+  DevState* state;
+  bool have_eps;
+  double eps;  // 1/m^2
+  int hist_len;
+  hipEvent_t ev0, ev1;
+};
+
+namespace {
+
+struct Layout {
+  size_t W, V0, twx, twy, twz, phase, partials, setup, hist, state, total;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int padded_pitch(int nx) { return (nx + 7) / 8 * 8; }
+
+bool layout_of(int nx, int ny, int nz, Layout& L) {
+  const SizeOps* ox = find_size(nx);
+  if (!ox) return false;
+  const long long N = (long long)nx * ny * nz;
+  const long long rows = (long long)ny * nz;
+  const long long k1b = (rows + ox->k1_lines - 1) / ox->k1_lines;
+  const size_t c8 = sizeof(float2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.W = take((size_t)3 * nz * ny * padded_pitch(nx) * c8);
+  L.V0 = take((size_t)N * c8);
+  L.twx = take((size_t)nx * c8);
+  L.twy = take((size_t)ny * c8);
+  L.twz = take((size_t)nz * c8);
+  L.phase = take((size_t)nz * c8);
+  L.partials = take((size_t)2 * k1b * sizeof(double));
+  L.setup = take((size_t)2 * kSetupBlocks * sizeof(double));
+  L.hist = take((size_t)kHistCap * sizeof(double));
+  L.state = take(sizeof(DevState));
+  L.total = off;
+  return true;
+}
+
+void fill_twiddles(std::vector<float2>& t, int n) {
+  t.resize(n);
+  for (int m = 0; m < n; ++m) {
+    const double ang = -2.0 * M_PI * double(m) / double(n);
+    t[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+}
+
+CbsArgs base_args(cbs_plan_s* p) {
+  CbsArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.nx = p->nx;
+  a.ny = p->ny;
+  a.nz = p->nz;
+  a.nxp = p->nxp;
+  a.px = p->pml[0];
+  a.py = p->pml[1];
+  a.pz = p->pml[2];
+  a.sW = (long long)p->nz * p->ny * p->nxp;
+  a.sE = (long long)p->nz * p->ny * p->nx;
+  a.W = p->W;
+  a.V0 = p->V0;
+  a.twx = p->twx;
+  a.twy = p->twy;
+  a.twz = p->twz;
+  a.phase = p->phase;
+  a.partials = p->partials;
+  a.hist = p->hist;
+  a.st = p->state;
+  const double d2 = p->pitch * p->pitch;
+  a.eps = (float)(p->eps * d2);
+  a.inv_eps = (float)(1.0 / (p->eps * d2));
+  a.kb2 = (float)(p->kb * p->kb * d2);
+  a.pfx = (float)(2.0 * M_PI / p->nx);
+  a.pfy = (float)(2.0 * M_PI / p->ny);
+  a.pfz = (float)(2.0 * M_PI / p->nz);
+  a.invN = (float)(1.0 / ((double)p->nx * p->ny * p->nz));
+  a.src_scale = (float)d2;
+  a.pol[0] = make_float2(1.f, 0.f);
+  return a;
+}
+
+int check_plan(cbs_plan_t p, bool need_eps) {
+  if (!p) return fail(CBS_E_INVALID, "null plan");
+  if (need_eps && !p->have_eps)
+    return fail(CBS_E_STATE, "cbs_set_permittivity must be called before solving");
+  return CBS_OK;
+}
+
+int check_opts(const cbs_opts* o) {
+  if (!o) return fail(CBS_E_INVALID, "opts is NULL");
+  if (o->max_iter < 1) return fail(CBS_E_INVALID, "max_iter must be >= 1 (got %d)", o->max_iter);
+  if (o->check_every < 1) return fail(CBS_E_INVALID, "check_every must be >= 1");
+  if (!(o->tol >= 0.0)) return fail(CBS_E_INVALID, "tol must be >= 0");
+  return CBS_OK;
+}
+
+// one CBS iteration: y forward, z forward + Green + z inverse, y inverse,
+// x inverse + update + next forward x, residual
+int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
+  p->oy->ky(a, -1, p->stream);
+  p->oz->kz(a, p->stream);
+  p->oy->ky(a, +1, p->stream);
+  p->ox->k1(a, K1_ITER, p->stream);
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
+                     p->k1_blocks, p->state, p->hist);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// prologue + iteration loop with device-side stopping and periodic host polls
+int run_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, cbs_stats* stats) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, o->tol,
+                     o->max_iter, (o->flags & CBS_RECORD_HISTORY) ? 1 : 0);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+int iterate(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, cbs_stats* stats) {
+  HIP_TRY(hipEventRecord(p->ev0, p->stream));
+  p->ox->k1(a, K1_FWD, p->stream);
+  HIP_LAUNCHED();
+  DevState hs;
+  int done_iters = 0;
+  bool finished = false;
+  while (done_iters < o->max_iter) {
+    const int q = std::min(o->check_every, o->max_iter - done_iters);
+    for (int i = 0; i < q; ++i) {
+      int rc = enqueue_iteration(p, a);
+      if (rc != CBS_OK) return rc;
+    }
+    done_iters += q;
+    HIP_TRY(hipMemcpyAsync(&hs, p->state, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (hs.done) {
+      finished = true;
+      break;
+    }
+  }
+  (void)finished;
+  HIP_TRY(hipEventRecord(p->ev1, p->stream));
+  HIP_TRY(hipEventSynchronize(p->ev1));
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  HIP_TRY(hipMemcpy(&hs, p->state, sizeof(DevState), hipMemcpyDeviceToHost));
+  p->hist_len = (o->flags & CBS_RECORD_HISTORY) ? std::min(hs.iter, kHistCap) : 0;
+  if (stats) {
+    stats->iterations = hs.iter;
+    stats->converged = hs.status == 1;
+    stats->residual = hs.eta;
+    stats->eps_shift = p->eps;
+    stats->ms = ms;
+  }
+  if (hs.status == 3) return fail(CBS_E_DIVERGED, "non-finite residual after %d iterations", hs.iter);
+  if (hs.status == 1) return CBS_OK;
+  g_err = "max_iter reached before the residual met tol";
+  return CBS_NOT_CONVERGED;
+}
+
+int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, float2 pol[3]) {
+  const int kind = src ? src->kind : CBS_SRC_PLANE_WAVE;
+  pol[0] = make_float2(1.f, 0.f);
+  pol[1] = pol[2] = make_float2(0.f, 0.f);
+  switch (kind) {
+    case CBS_SRC_NONE:
+      a.src = SRC_NONE;
+      break;
+    case CBS_SRC_PLANE_WAVE: {
+      if (adjoint) return fail(CBS_E_INVALID, "adjoint source cannot be a plane wave");
+      a.src = SRC_PLANE;
+      if (src) {
+        bool any = false;
+        for (int c = 0; c < 3; ++c) any |= (src->pol[c][0] != 0.0 || src->pol[c][1] != 0.0);
+        if (any)
+          for (int c = 0; c < 3; ++c)
+            pol[c] = make_float2((float)src->pol[c][0], (float)src->pol[c][1]);
+      }
+      break;
+    }
+    case CBS_SRC_FIELD:
+      if (!src->field) return fail(CBS_E_INVALID, "FIELD source without a field pointer");
+      a.src = SRC_FIELD;
+      a.fin = static_cast<const float2*>(src->field);
+      break;
+    case CBS_SRC_POINT:
+      for (int c = 0; c < 3; ++c) {
+        const int n = c == 0 ? p->nx : (c == 1 ? p->ny : p->nz);
+        if (src->r0[c] < 0 || src->r0[c] >= n)
+          return fail(CBS_E_INVALID, "point source r0[%d]=%d outside [0,%d)", c, src->r0[c], n);
+      }
+      a.src = SRC_POINT;
+      a.r0x = src->r0[0];
+      a.r0y = src->r0[1];
+      a.r0z = src->r0[2];
+      break;
+    default:
+      return fail(CBS_E_INVALID, "unknown source kind %d", kind);
+  }
+  a.pol[0] = pol[0];
+  a.pol[1] = pol[1];
+  a.pol[2] = pol[2];
+  return CBS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t cbs_plan_workspace_bytes(int nx, int ny, int nz) {
+  if (nx < 2 || ny < 2 || nz < 2) return 0;
+  if (!cbs_axis_supported(0, nx) || !cbs_axis_supported(1, ny) || !cbs_axis_supported(2, nz))
+    return 0;
+  Layout L;
+  if (!layout_of(nx, ny, nz, L)) return 0;
+  return L.total;
+}
+
+int cbs_axis_supported(int axis, int n) {
+  const SizeOps* o = find_size(n);
+  if (!o) return 0;
+  if (axis == 2) return o->kz != nullptr;
+  return (axis == 0 || axis == 1) ? 1 : 0;
+}
+
+int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, double lambda0_m,
+                    double n_bg, const int pml[3], void* workspace, size_t workspace_bytes,
+                    void* stream) {
+  if (!out) return fail(CBS_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || nz < 2) return fail(CBS_E_INVALID, "grid %dx%dx%d: each axis must be >= 2", nx, ny, nz);
+  const int dims[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    if (!cbs_axis_supported(a, dims[a]))
+      return fail(CBS_E_INVALID, "axis %d length %d has no FFT specialisation", a, dims[a]);
+  if (!(pitch_m > 0) || !std::isfinite(pitch_m)) return fail(CBS_E_INVALID, "pitch must be > 0");
+  if (!(lambda0_m > 0) || !std::isfinite(lambda0_m)) return fail(CBS_E_INVALID, "lambda0 must be > 0");
+  if (!(n_bg > 0) || !std::isfinite(n_bg)) return fail(CBS_E_INVALID, "n_bg must be > 0");
+  int pm[3] = {0, 0, 0};
+  if (pml)
+    for (int a = 0; a < 3; ++a) {
+      pm[a] = pml[a];
+      if (pm[a] < 0 || 2 * pm[a] >= dims[a])
+        return fail(CBS_E_INVALID, "pml[%d]=%d must satisfy 0 <= 2 pml < %d", a, pm[a], dims[a]);
+    }
+  Layout L;
+  layout_of(nx, ny, nz, L);
+  if (!workspace) return fail(CBS_E_WORKSPACE, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+    return fail(CBS_E_WORKSPACE, "workspace must be 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return fail(CBS_E_WORKSPACE, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+
+  cbs_plan_s* p = new (std::nothrow) cbs_plan_s();
+  if (!p) return fail(CBS_E_INVALID, "out of host memory");
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->nxp = padded_pitch(nx);
+  for (int a = 0; a < 3; ++a) p->pml[a] = pm[a];
+  p->pitch = pitch_m;
+  p->lambda0 = lambda0_m;
+  p->n_bg = n_bg;
+  p->k0 = 2.0 * M_PI / lambda0_m;
+  p->kb = p->k0 * n_bg;
+  p->order = 2;
+  p->sigma_max = 1.0;
+  p->shift_factor = 1.1;
+  p->ox = find_size(nx);
+  p->oy = find_size(ny);
+  p->oz = find_size(nz);
+  p->k1_blocks = (int)(((long long)ny * nz + p->ox->k1_lines - 1) / p->ox->k1_lines);
+  p->stream = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(workspace);
+  p->W = reinterpret_cast<float2*>(base + L.W);
+  p->V0 = reinterpret_cast<float2*>(base + L.V0);
+  p->twx = reinterpret_cast<float2*>(base + L.twx);
+  p->twy = reinterpret_cast<float2*>(base + L.twy);
+  p->twz = reinterpret_cast<float2*>(base + L.twz);
+  p->phase = reinterpret_cast<float2*>(base + L.phase);
+  p->partials = reinterpret_cast<double*>(base + L.partials);
+  p->setup_part = reinterpret_cast<double*>(base + L.setup);
+  p->hist = reinterpret_cast<double*>(base + L.hist);
+  p->state = reinterpret_cast<DevState*>(base + L.state);
+  p->have_eps = false;
+  p->eps = -1.0;
+  p->hist_len = 0;
+
+  std::vector<float2> tx, ty, tz, ph(nz);
+  fill_twiddles(tx, nx);
+  fill_twiddles(ty, ny);
+  fill_twiddles(tz, nz);
+  for (int k = 0; k < nz; ++k) {
+    const double ang = p->kb * pitch_m * k;
+    ph[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  auto cleanup = [&](int rc) {
+    delete p;
+    return rc;
+  };
+  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+    return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
+  hipError_t e = hipSuccess;
+  e = e == hipSuccess ? hipMemcpyAsync(p->twx, tx.data(), nx * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  e = e == hipSuccess ? hipMemcpyAsync(p->twy, ty.data(), ny * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  e = e == hipSuccess ? hipMemcpyAsync(p->twz, tz.data(), nz * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  e = e == hipSuccess ? hipMemcpyAsync(p->phase, ph.data(), nz * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  e = e == hipSuccess ? hipMemsetAsync(p->W, 0, L.V0 - L.W, p->stream) : e;
+  e = e == hipSuccess ? hipMemsetAsync(p->state, 0, sizeof(DevState), p->stream) : e;
+  e = e == hipSuccess ? hipStreamSynchronize(p->stream) : e;
+  if (e != hipSuccess) {
+    hipEventDestroy(p->ev0);
+    hipEventDestroy(p->ev1);
+    return cleanup(fail(CBS_E_HIP, "plan upload: %s", hipGetErrorString(e)));
+  }
+  *out = p;
+  return CBS_OK;
+}
+
+int cbs_plan_set_pml_profile(cbs_plan_t p, int order, double sigma_max) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (order < 1 || order > 8) return fail(CBS_E_INVALID, "order must be in [1, 8]");
+  if (!(sigma_max >= 0) || !std::isfinite(sigma_max)) return fail(CBS_E_INVALID, "sigma_max must be >= 0");
+  p->order = order;
+  p->sigma_max = sigma_max;
+  p->have_eps = false;
+  p->eps = -1.0;
+  return CBS_OK;
+}
+
+int cbs_plan_set_shift_factor(cbs_plan_t p, double kappa) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!(kappa >= 1.0) || !std::isfinite(kappa)) return fail(CBS_E_INVALID, "shift factor must be >= 1 (got %g)", kappa);
+  p->shift_factor = kappa;
+  p->have_eps = false;
+  p->eps = -1.0;
+  return CBS_OK;
+}
+
+int cbs_set_permittivity(cbs_plan_t p, const void* eps_r, int dtype) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!eps_r) return fail(CBS_E_INVALID, "eps_r is NULL");
+  if (dtype != CBS_F32 && dtype != CBS_C64) return fail(CBS_E_INVALID, "dtype must be CBS_F32 or CBS_C64");
+  p->have_eps = false;
+  SetupArgs s;
+  s.nx = p->nx;
+  s.ny = p->ny;
+  s.nz = p->nz;
+  s.px = p->pml[0];
+  s.py = p->pml[1];
+  s.pz = p->pml[2];
+  s.order = p->order;
+  s.dtype = dtype;
+  s.sigma_max = p->sigma_max;
+  const double d2 = p->pitch * p->pitch;
+  s.k0d2 = p->k0 * p->k0 * d2;
+  s.kbd2 = p->kb * p->kb * d2;
+  s.nb2 = p->n_bg * p->n_bg;
+  s.nb2f = (float)(p->n_bg * p->n_bg);
+  s.eps = eps_r;
+  s.V0 = p->V0;
+  s.part = p->setup_part;
+  hipLaunchKernelGGL(k_setup, dim3(kSetupBlocks), dim3(kSetupThreads), 0, p->stream, s);
+  HIP_LAUNCHED();
+  std::vector<double> part(2 * kSetupBlocks);
+  HIP_TRY(hipMemcpyAsync(part.data(), p->setup_part, part.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double mx = 0.0;
+  unsigned fl = 0;
+  for (int b = 0; b < kSetupBlocks; ++b) {
+    mx = part[2 * b] > mx ? part[2 * b] : mx;
+    fl |= (unsigned)part[2 * b + 1];
+  }
+  if (fl & 1u) return fail(CBS_E_INVALID, "eps_r has non-finite values");
+  if (fl & 2u) return fail(CBS_E_INVALID, "gain medium (Im eps_r < 0) is not admissible");
+  if (fl & 4u) return fail(CBS_E_INVALID, "eps_r must equal n_bg^2 inside the absorbing layer");
+  const double floor_ = 1e-3 * p->kb * p->kb * d2;
+  const double eps_d2 = p->shift_factor * (mx > floor_ ? mx : floor_);
+  p->eps = eps_d2 / d2;
+  p->have_eps = true;
+  return CBS_OK;
+}
+
+double cbs_eps_shift(cbs_plan_t p) { return (p && p->have_eps) ? p->eps : -1.0; }
+
+int cbs_solve(cbs_plan_t p, const cbs_source* src, void* E_dev, const cbs_opts* o,
+              cbs_stats* stats) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!E_dev) return fail(CBS_E_INVALID, "E is NULL");
+  CbsArgs a = base_args(p);
+  float2 pol[3];
+  if ((rc = set_source(p, a, src, false, pol))) return rc;
+  a.E = static_cast<float2*>(E_dev);
+  const bool plane = a.src == SRC_PLANE;
+  const bool warm = (o->flags & CBS_WARM_START) != 0;
+  if ((rc = run_solve(p, a, o, stats))) return rc;
+  if (a.src == SRC_POINT) {
+    hipLaunchKernelGGL(k_point_amp, dim3(1), dim3(64), 0, p->stream, p->state,
+                       (const float2*)nullptr, 0LL, a.sE, 0, (float)(p->pitch * p->pitch),
+                       make_float2((float)src->amp[0][0], (float)src->amp[0][1]),
+                       make_float2((float)src->amp[1][0], (float)src->amp[1][1]),
+                       make_float2((float)src->amp[2][0], (float)src->amp[2][1]));
+    HIP_LAUNCHED();
+  }
+  const int gb = 2048, tb = 256;
+  if (warm && plane) {
+    hipLaunchKernelGGL(k_incident, dim3(gb), dim3(tb), 0, p->stream, a.E, p->phase, p->nx,
+                       p->ny, p->nz, pol[0], pol[1], pol[2], -1.0f);
+    HIP_LAUNCHED();
+  }
+  a.warm = warm ? 1 : 0;
+  rc = iterate(p, a, o, stats);
+  if (rc < 0) return rc;
+  if (plane && !(o->flags & CBS_RETURN_SCATTERED)) {
+    hipLaunchKernelGGL(k_incident, dim3(gb), dim3(tb), 0, p->stream, a.E, p->phase, p->nx,
+                       p->ny, p->nz, pol[0], pol[1], pol[2], 1.0f);
+    HIP_LAUNCHED();
+    HIP_TRY(hipStreamSynchronize(p->stream));
+  }
+  return rc;
+}
+
+int cbs_adjoint_solve(cbs_plan_t p, const void* E_fwd, const cbs_source* adj, void* E_adj,
+                      const cbs_opts* o, cbs_stats* stats) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!E_adj) return fail(CBS_E_INVALID, "E_adj is NULL");
+  if (!adj) return fail(CBS_E_INVALID, "adjoint source is NULL");
+  if (adj->kind != CBS_SRC_POINT && adj->kind != CBS_SRC_FIELD)
+    return fail(CBS_E_INVALID, "adjoint source must be POINT or FIELD");
+  CbsArgs a = base_args(p);
+  float2 pol[3];
+  if ((rc = set_source(p, a, adj, true, pol))) return rc;
+  a.E = static_cast<float2*>(E_adj);
+  a.warm = (o->flags & CBS_WARM_START) ? 1 : 0;
+  if ((rc = run_solve(p, a, o, stats))) return rc;
+  if (a.src == SRC_POINT) {
+    const long long idx = ((long long)adj->r0[2] * p->ny + adj->r0[1]) * p->nx + adj->r0[0];
+    hipLaunchKernelGGL(k_point_amp, dim3(1), dim3(64), 0, p->stream, p->state,
+                       static_cast<const float2*>(E_fwd), idx, a.sE, E_fwd ? 1 : 0,
+                       (float)(p->pitch * p->pitch),
+                       make_float2((float)adj->amp[0][0], (float)adj->amp[0][1]),
+                       make_float2((float)adj->amp[1][0], (float)adj->amp[1][1]),
+                       make_float2((float)adj->amp[2][0], (float)adj->amp[2][1]));
+    HIP_LAUNCHED();
+  }
+  return iterate(p, a, o, stats);
+}
+
+int cbs_gradient(cbs_plan_t p, const void* E, const void* Ea, const int lo[3], const int hi[3],
+                 double scale, float* grad) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!E || !Ea || !grad || !lo || !hi) return fail(CBS_E_INVALID, "NULL argument");
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || hi[a] > dims[a] || lo[a] > hi[a])
+      return fail(CBS_E_INVALID, "box axis %d [%d,%d) outside [0,%d)", a, lo[a], hi[a], dims[a]);
+  const int bx = hi[0] - lo[0], by = hi[1] - lo[1], bz = hi[2] - lo[2];
+  if ((long long)bx * by * bz == 0) return CBS_OK;
+  hipLaunchKernelGGL(k_gradient, dim3(2048), dim3(256), 0, p->stream,
+                     static_cast<const float2*>(E), static_cast<const float2*>(Ea),
+                     (long long)p->nx * p->ny * p->nz, p->nx, p->ny, lo[0], lo[1], lo[2], bx, by,
+                     bz, scale * p->k0 * p->k0, grad);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+int cbs_apply_green(cbs_plan_t p, const void* in, void* out) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if (!in || !out) return fail(CBS_E_INVALID, "NULL field");
+  if (in == out) return fail(CBS_E_INVALID, "in and out must not alias");
+  CbsArgs a = base_args(p);
+  a.green_in = 1;
+  a.fin = static_cast<const float2*>(in);
+  a.fout = static_cast<float2*>(out);
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, 0.0, 1, 0);
+  HIP_LAUNCHED();
+  p->ox->k1(a, K1_FWD, p->stream);
+  p->oy->ky(a, -1, p->stream);
+  p->oz->kz(a, p->stream);
+  p->oy->ky(a, +1, p->stream);
+  p->ox->k1(a, K1_INV, p->stream);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+int cbs_history(cbs_plan_t p, double* out, int max) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  const int n = std::min(max, p->hist_len);
+  if (n > 0 && out)
+    HIP_TRY(hipMemcpy(out, p->hist, n * sizeof(double), hipMemcpyDeviceToHost));
+  return p->hist_len;
+}
+
+int cbs_plan_destroy(cbs_plan_t p) {
+  if (!p) return CBS_OK;
+  hipEventDestroy(p->ev0);
+  hipEventDestroy(p->ev1);
+  delete p;
+  return CBS_OK;
+}
+
+const char* cbs_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

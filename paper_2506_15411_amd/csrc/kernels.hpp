@@ -1,0 +1,496 @@
+// CBS iteration kernels for gfx950.
+//
+// One CBS iteration (vector CBS of references [25]/[26] of arXiv 2506.15411)
+//     W = V E_s + S;  GW = F^-1 G^ F W;  E_s += gamma (GW - E_s)
+// runs as four passes over HBM, each a batch of 1D FFTs along one axis:
+//
+//   KY(-)  forward FFT along y                               (W in place)
+//   KZ     forward FFT along z, G^(p) 3x3 multiply (1/N folded in),
+//          inverse FFT along z; all three components of a z-column
+//          are in one workgroup                              (W in place)
+//   KY(+)  inverse FFT along y                               (W in place)
+//   K1     inverse FFT along x -> GW, CBS update of E_s with FP64 residual
+//          partials, W = V E_s + S for the next iteration, forward FFT
+//          along x                                           (W, E_s)
+//
+// Every 1D transform of length n = N1 * N2 is two register levels joined by
+// one exchange through LDS: level A does N2 DFT-N1 over stride-N2 subsets
+// (one per thread) and multiplies by exp(-+2 pi i j2 k1 / n); level B does
+// N1 DFT-N2 over the contiguous groups (one per thread).  Level A writes its
+// results to the LDS slots its inputs came from, so each exchange needs one
+// buffer and one barrier.  In K1 the inverse transform ends with thread t
+// holding GW[t + N1 m]; the forward transform of the next W is chosen with
+// the transposed split (DFT-N2 over exactly those elements first), so the
+// update and the start of the forward transform run in registers without an
+// LDS round trip.  In KZ the forward level B leaves each thread with all
+// z-frequencies k1 + N1 k2 of its group for the three components, the Green
+// multiply and the inverse level B run on those registers, and the z
+// spectrum is never reordered.
+//
+// Work is in units of the voxel pitch: lengths are scaled by 1/d, potentials
+// by d^2 (p d in [-pi, pi], kb^2 d^2, eps d^2), which leaves E_s unchanged.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "codelets.hpp"
+
+namespace cbs {
+
+enum SrcKind : int { SRC_NONE = 0, SRC_PLANE = 1, SRC_FIELD = 2, SRC_POINT = 3 };
+enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
+
+constexpr int kHistCap = 1 << 16;
+
+// Device-resident solve state (lives in the workspace).
+struct DevState {
+  int done;        // 1: stop iterating (kernels return at entry)
+  int iter;        // iterations applied
+  int status;      // 0 running, 1 converged, 2 max_iter, 3 diverged
+  int max_iter;
+  double tol;
+  double eta;      // last relative update norm
+  float2 amp[3];   // point-source amplitude (already scaled by d^2)
+  int record;      // keep eta history
+  int pad;
+};
+
+struct CbsArgs {
+  int nx, ny, nz, nxp;          // grid, padded row pitch of W
+  int px, py, pz;               // absorbing layer per side
+  long long sW;                 // component stride of W  (nz * ny * nxp)
+  long long sE;                 // component stride of E  (nz * ny * nx)
+  float2* W;                    // spectral work field [3][nz][ny][nxp]
+  float2* E;                    // E_s, caller layout [3][nz][ny][nx]
+  const float2* V0;             // unshifted potential * d^2, [nz][ny][nx]
+  const float2* twx;            // exp(-2 pi i m / nx), m < nx
+  const float2* twy;
+  const float2* twz;
+  const float2* phase;          // exp(i kb d k), k < nz
+  const float2* fin;            // FIELD source / Green input
+  float2* fout;                 // Green output
+  double* partials;             // 2 doubles per K1 block
+  double* hist;                 // residual history
+  DevState* st;
+  int src;                      // SrcKind
+  int warm;                     // K1_FWD: W = V E + S from E (else E = 0)
+  int green_in;                 // K1_FWD: W = fin
+  int r0x, r0y, r0z;
+  float2 pol[3];
+  float src_scale;              // d^2: physical (1/m^2) sources and Green inputs
+  float eps, inv_eps, kb2;      // eps d^2, 1/(eps d^2), kb^2 d^2
+  float pfx, pfy, pfz;          // 2 pi / n_a
+  float invN;                   // 1 / (nx ny nz)
+};
+
+// ---------------------------------------------------------------------------
+// per-size geometry of the passes
+// ---------------------------------------------------------------------------
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int round64(int t) { return (t + 63) / 64 * 64; }
+
+template <int N1, int N2>
+struct XGeom {
+  static constexpr int N = N1 * N2;
+  static constexpr int TM = cmax(N1, N2);
+  static constexpr int LINES = cmax(1, 256 / (3 * TM));
+  static constexpr int THREADS = round64(3 * LINES * TM);
+};
+template <int N1, int N2, int TX>
+struct YGeom {
+  static constexpr int N = N1 * N2;
+  static constexpr int TM = cmax(N1, N2);
+  static constexpr int THREADS = round64(TX * TM);
+};
+template <int N1, int N2, int TX>
+struct ZGeom {
+  static constexpr int N = N1 * N2;
+  static constexpr int TM = cmax(3 * N2, N1);
+  static constexpr int THREADS = round64(TX * TM);
+};
+
+// dimensionless frequency 2 pi m / n of FFT index k (m in FFT order) and the
+// same with the Nyquist index of an even axis flagged
+__device__ __forceinline__ float freq_of(int k, int n, float pf, bool& nyq) {
+  const int m = (k < (n + 1) / 2) ? k : k - n;
+  nyq = ((n & 1) == 0) && (2 * k == n);
+  return pf * float(m);
+}
+
+// ---------------------------------------------------------------------------
+// block reduction of two doubles (residual partials)
+// ---------------------------------------------------------------------------
+template <int THREADS>
+__device__ __forceinline__ void block_sum2(double a, double b, double* red, double* out) {
+  #pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[2 * wv] = a;
+    red[2 * wv + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double sa = 0.0, sb = 0.0;
+    for (int w = 0; w < THREADS / 64; ++w) {
+      sa += red[2 * w];
+      sb += red[2 * w + 1];
+    }
+    out[0] = sa;
+    out[1] = sb;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K1: x-pass with the fused CBS update
+// ---------------------------------------------------------------------------
+template <int N1, int N2, int MODE>
+__global__ void __launch_bounds__((XGeom<N1, N2>::THREADS))
+k1_xpass(CbsArgs a) {
+  using G = XGeom<N1, N2>;
+  constexpr int N = G::N, TM = G::TM, LINES = G::LINES;
+  __shared__ float2 lds[3 * LINES * N];
+  __shared__ float2 tw[N];
+  __shared__ double red[2 * (G::THREADS / 64)];
+
+  if (MODE == K1_ITER && a.st->done) return;
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
+
+  const int t = tid % TM;
+  const int cl = tid / TM;
+  const int c = cl / LINES;
+  const int line = cl - c * LINES;
+  const long long nrows = (long long)a.ny * a.nz;
+  const long long row = (long long)blockIdx.x * LINES + line;
+  const bool ok = (cl < 3 * LINES) && (row < nrows);
+  const int cc = ok ? c : 0;
+  const long long rr = ok ? row : 0;
+  const int z = (int)(rr / a.ny);
+  const int y = (int)(rr - (long long)z * a.ny);
+  float2* L = lds + (cl < 3 * LINES ? cl : 0) * N;
+  float2* Wrow = a.W + cc * a.sW + rr * a.nxp;
+  const long long ebase = cc * a.sE + rr * a.nx;  // E / fin / fout row
+  const long long vbase = rr * a.nx;              // V0 row
+  __syncthreads();
+
+  float2 v[N2];  // thread t (< N1): element t + N1 m, m < N2
+  if constexpr (MODE != K1_FWD) {
+    // inverse level A: thread j2 = t < N2, DFT-N1 over Wrow[j2 + N2 j1]
+    if (ok && t < N2) {
+      float2 b[N1];
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = Wrow[t + N2 * CV(J1)]; });
+      dft<N1, +1>(b);
+      int idx = 0;
+      sfor<0, N1>([&](auto K1) {
+        b[CV(K1)] = cmulc(b[CV(K1)], tw[idx]);
+        idx += t;
+        if (idx >= N) idx -= N;
+      });
+      sfor<0, N1>([&](auto K1) { L[t + N2 * CV(K1)] = b[CV(K1)]; });
+    }
+    __syncthreads();
+    // inverse level B: thread k1 = t < N1, DFT-N2 over L[N2 k1 + j2]
+    if (ok && t < N1) {
+      sfor<0, N2>([&](auto J2) { v[CV(J2)] = L[N2 * t + CV(J2)]; });
+      dft<N2, +1>(v);
+    }
+    __syncthreads();  // L is rewritten below
+  }
+
+  if constexpr (MODE == K1_INV) {
+    if (ok && t < N1) {
+      sfor<0, N2>([&](auto M) { a.fout[ebase + t + N1 * CV(M)] = v[CV(M)]; });
+    }
+    return;
+  }
+
+  double sd = 0.0, se = 0.0;
+  if (ok && t < N1) {
+    const bool yin = (y >= a.py) && (y < a.ny - a.py);
+    const bool zin = (z >= a.pz) && (z < a.nz - a.pz);
+    const float2 ph = a.phase[z];
+    const float2 pc = cc == 0 ? a.pol[0] : (cc == 1 ? a.pol[1] : a.pol[2]);
+    const float2 spl = cmul(ph, pc);  // pol_c exp(i kb z)
+    sfor<0, N2>([&](auto M) {
+      const int x = t + N1 * CV(M);
+      float2 e;
+      const float2 v0 = a.V0[vbase + x];
+      if constexpr (MODE == K1_ITER) {
+        e = a.E[ebase + x];
+        // gamma = 1 + i V0 / eps
+        const float2 gm = make_float2(1.0f - v0.y * a.inv_eps, v0.x * a.inv_eps);
+        const float2 d = cmul(gm, csub(v[CV(M)], e));
+        e = cadd(e, d);
+        sd += (double)(d.x * d.x + d.y * d.y);
+        se += (double)(e.x * e.x + e.y * e.y);
+        a.E[ebase + x] = e;
+      } else {
+        e = a.warm ? a.E[ebase + x] : make_float2(0.f, 0.f);
+      }
+      float2 w;
+      if (MODE == K1_FWD && a.green_in) {
+        w = cscale(a.fin[ebase + x], a.src_scale);
+      } else {
+        // W = (V0 - i eps) e + S
+        w = cmul(make_float2(v0.x, v0.y - a.eps), e);
+        if (a.src == SRC_PLANE) {
+          const bool xin = (x >= a.px) && (x < a.nx - a.px);
+          if (xin && yin && zin) w = cadd(w, cmul(v0, spl));
+        } else if (a.src == SRC_FIELD) {
+          w = cadd(w, cscale(a.fin[ebase + x], a.src_scale));
+        } else if (a.src == SRC_POINT) {
+          if (x == a.r0x && y == a.r0y && z == a.r0z) w = cadd(w, a.st->amp[cc]);
+        }
+      }
+      v[CV(M)] = w;
+    });
+    // forward level A' (split N2 x N1): DFT-N2 over v, twiddle, to L[t + N1 k1']
+    dft<N2, -1>(v);
+    int idx = 0;
+    sfor<0, N2>([&](auto K) {
+      L[t + N1 * CV(K)] = cmul(v[CV(K)], tw[idx]);
+      idx += t;
+      if (idx >= N) idx -= N;
+    });
+  }
+  __syncthreads();
+  // forward level B': thread k1' = t < N2, DFT-N1 over L[N1 k1' + j2']
+  if (ok && t < N2) {
+    float2 b[N1];
+    sfor<0, N1>([&](auto J) { b[CV(J)] = L[N1 * t + CV(J)]; });
+    dft<N1, -1>(b);
+    sfor<0, N1>([&](auto K) { Wrow[t + N2 * CV(K)] = b[CV(K)]; });
+  }
+  if constexpr (MODE == K1_ITER) {
+    block_sum2<G::THREADS>(sd, se, red, a.partials + 2 * (long long)blockIdx.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KY: FFT along y of TX adjacent columns of one (component, z) plane
+// ---------------------------------------------------------------------------
+template <int N1, int N2, int TX, int S>
+__global__ void __launch_bounds__((YGeom<N1, N2, TX>::THREADS))
+ky_pass(CbsArgs a) {
+  using G = YGeom<N1, N2, TX>;
+  constexpr int N = G::N;
+  __shared__ float2 lds[N * TX];
+  __shared__ float2 tw[N];
+  if (a.st->done) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
+  const int xi = tid % TX;
+  const int t = tid / TX;
+  const int x = blockIdx.x * TX + xi;
+  const bool xok = x < a.nx;
+  const int z = blockIdx.y, c = blockIdx.z;
+  float2* col = a.W + c * a.sW + (long long)z * a.ny * a.nxp + (xok ? x : 0);
+  const long long ps = a.nxp;
+  __syncthreads();
+  if (t < N2) {
+    float2 b[N1];
+    if (xok) {
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[(t + N2 * CV(J1)) * ps]; });
+    } else {
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+    }
+    dft<N1, S>(b);
+    int idx = 0;
+    sfor<0, N1>([&](auto K1) {
+      const float2 w = tw[idx];
+      b[CV(K1)] = (S < 0) ? cmul(b[CV(K1)], w) : cmulc(b[CV(K1)], w);
+      idx += t;
+      if (idx >= N) idx -= N;
+    });
+    sfor<0, N1>([&](auto K1) { lds[(t + N2 * CV(K1)) * TX + xi] = b[CV(K1)]; });
+  }
+  __syncthreads();
+  if (t < N1 && xok) {
+    float2 v[N2];
+    sfor<0, N2>([&](auto J2) { v[CV(J2)] = lds[(N2 * t + CV(J2)) * TX + xi]; });
+    dft<N2, S>(v);
+    sfor<0, N2>([&](auto K2) { col[(t + N1 * CV(K2)) * ps] = v[CV(K2)]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// KZ: FFT along z, Green's tensor, inverse FFT along z (3 components)
+// ---------------------------------------------------------------------------
+template <int N1, int N2, int TX>
+__global__ void __launch_bounds__((ZGeom<N1, N2, TX>::THREADS))
+kz_pass(CbsArgs a) {
+  using G = ZGeom<N1, N2, TX>;
+  constexpr int N = G::N;
+  __shared__ float2 lds[3 * N * TX];
+  __shared__ float2 tw[N];
+  if (a.st->done) return;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
+  const int xi = tid % TX;
+  const int t = tid / TX;
+  const int x = blockIdx.x * TX + xi;
+  const bool xok = x < a.nx;
+  const int y = blockIdx.y;
+  const long long plane = (long long)a.ny * a.nxp;
+  float2* colbase = a.W + (long long)y * a.nxp + (xok ? x : 0);
+  __syncthreads();
+
+  // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
+  const int ca = t / N2;
+  const int j2 = t - ca * N2;
+  if (t < 3 * N2) {
+    float2* col = colbase + ca * a.sW;
+    float2 b[N1];
+    if (xok) {
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[(j2 + N2 * CV(J1)) * plane]; });
+    } else {
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+    }
+    dft<N1, -1>(b);
+    int idx = 0;
+    sfor<0, N1>([&](auto K1) {
+      b[CV(K1)] = cmul(b[CV(K1)], tw[idx]);
+      idx += j2;
+      if (idx >= N) idx -= N;
+    });
+    float2* Lc = lds + ca * N * TX;
+    sfor<0, N1>([&](auto K1) { Lc[(j2 + N2 * CV(K1)) * TX + xi] = b[CV(K1)]; });
+  }
+  __syncthreads();
+
+  // level B: thread k1 = t, all three components, Green multiply, inverse B
+  if (t < N1) {
+    float2 v0[N2], v1[N2], v2[N2];
+    float2* L0 = lds;
+    float2* L1 = lds + N * TX;
+    float2* L2 = lds + 2 * N * TX;
+    sfor<0, N2>([&](auto J) {
+      const int o = (N2 * t + CV(J)) * TX + xi;
+      v0[CV(J)] = L0[o];
+      v1[CV(J)] = L1[o];
+      v2[CV(J)] = L2[o];
+    });
+    dft<N2, -1>(v0);
+    dft<N2, -1>(v1);
+    dft<N2, -1>(v2);
+    bool nyx, nyy;
+    const float px = freq_of(x, a.nx, a.pfx, nyx);
+    const float py = freq_of(y, a.ny, a.pfy, nyy);
+    const float ptx = nyx ? 0.f : px, pty = nyy ? 0.f : py;
+    const float pxy2 = px * px + py * py;
+    const float nq_xy = (nyx ? px * px : 0.f) + (nyy ? py * py : 0.f);
+    const float eps = a.eps, e2 = eps * eps;
+    sfor<0, N2>([&](auto K2) {
+      constexpr int k2 = CV(K2);
+      bool nyz;
+      const float pz = freq_of(t + N1 * k2, a.nz, a.pfz, nyz);
+      const float ptz = nyz ? 0.f : pz;
+      const float p2 = pxy2 + pz * pz;
+      // a = invN / (p2 - kb2 - i eps), b = 1 / (p2 - |pt|^2 - kb2 - i eps)
+      const float r1 = p2 - a.kb2;
+      const float s1 = a.invN / (r1 * r1 + e2);
+      const float2 ga = make_float2(r1 * s1, eps * s1);
+      const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
+      const float s2 = 1.0f / (r2 * r2 + e2);
+      const float2 gb = make_float2(r2 * s2, eps * s2);
+      const float2 u0 = v0[k2], u1 = v1[k2], u2 = v2[k2];
+      const float2 sp = make_float2(ptx * u0.x + pty * u1.x + ptz * u2.x,
+                                    ptx * u0.y + pty * u1.y + ptz * u2.y);
+      const float2 bs = cmul(gb, sp);
+      v0[k2] = cmul(ga, make_float2(u0.x + ptx * bs.x, u0.y + ptx * bs.y));
+      v1[k2] = cmul(ga, make_float2(u1.x + pty * bs.x, u1.y + pty * bs.y));
+      v2[k2] = cmul(ga, make_float2(u2.x + ptz * bs.x, u2.y + ptz * bs.y));
+    });
+    dft<N2, +1>(v0);
+    dft<N2, +1>(v1);
+    dft<N2, +1>(v2);
+    sfor<0, N2>([&](auto J) {
+      const int o = (N2 * t + CV(J)) * TX + xi;
+      L0[o] = v0[CV(J)];
+      L1[o] = v1[CV(J)];
+      L2[o] = v2[CV(J)];
+    });
+  }
+  __syncthreads();
+
+  // inverse level A: conj twiddle, inverse DFT-N1, store z = j2 + N2 j1
+  if (t < 3 * N2 && xok) {
+    float2* Lc = lds + ca * N * TX;
+    float2 b[N1];
+    sfor<0, N1>([&](auto K1) { b[CV(K1)] = Lc[(j2 + N2 * CV(K1)) * TX + xi]; });
+    int idx = 0;
+    sfor<0, N1>([&](auto K1) {
+      b[CV(K1)] = cmulc(b[CV(K1)], tw[idx]);
+      idx += j2;
+      if (idx >= N) idx -= N;
+    });
+    dft<N1, +1>(b);
+    float2* col = colbase + ca * a.sW;
+    sfor<0, N1>([&](auto J1) { col[(j2 + N2 * CV(J1)) * plane] = b[CV(J1)]; });
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers and the per-size registry
+// ---------------------------------------------------------------------------
+using LaunchK1 = void (*)(const CbsArgs&, int mode, hipStream_t);
+using LaunchKY = void (*)(const CbsArgs&, int sign, hipStream_t);
+using LaunchKZ = void (*)(const CbsArgs&, hipStream_t);
+
+struct SizeOps {
+  int n;
+  LaunchK1 k1;        // x axis
+  LaunchKY ky;        // y axis
+  LaunchKZ kz;        // z axis (nullptr: unsupported on z)
+  int k1_lines;       // rows per K1 block
+};
+
+constexpr int kTY = 8;   // columns per y-pass block
+constexpr int kTZ = 8;   // columns per z-pass block
+
+template <int N1, int N2>
+void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
+  using G = XGeom<N1, N2>;
+  const long long rows = (long long)a.ny * a.nz;
+  const unsigned nb = (unsigned)((rows + G::LINES - 1) / G::LINES);
+  if (mode == K1_FWD)
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD>), dim3(nb), dim3(G::THREADS), 0, s, a);
+  else if (mode == K1_ITER)
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_ITER>), dim3(nb), dim3(G::THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_INV>), dim3(nb), dim3(G::THREADS), 0, s, a);
+}
+
+template <int N1, int N2>
+void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
+  using G = YGeom<N1, N2, kTY>;
+  dim3 grid((a.nx + kTY - 1) / kTY, a.nz, 3);
+  if (sign < 0)
+    hipLaunchKernelGGL((ky_pass<N1, N2, kTY, -1>), grid, dim3(G::THREADS), 0, s, a);
+  else
+    hipLaunchKernelGGL((ky_pass<N1, N2, kTY, +1>), grid, dim3(G::THREADS), 0, s, a);
+}
+
+template <int N1, int N2>
+void launch_kz(const CbsArgs& a, hipStream_t s) {
+  using G = ZGeom<N1, N2, kTZ>;
+  dim3 grid((a.nx + kTZ - 1) / kTZ, a.ny, 1);
+  hipLaunchKernelGGL((kz_pass<N1, N2, kTZ>), grid, dim3(G::THREADS), 0, s, a);
+}
+
+#define CBS_SIZE_XYZ(n, a1, a2, z1, z2) \
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, XGeom<a1, a2>::LINES }
+#define CBS_SIZE_XY(n, a1, a2) \
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, XGeom<a1, a2>::LINES }
+
+// registry, defined in the size translation units
+const SizeOps* find_size(int n);
+
+}  // namespace cbs

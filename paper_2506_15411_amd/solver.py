@@ -1,0 +1,195 @@
+"""Torch-facing wrapper of libcbs: device memory and streams come from torch,
+every arithmetic step runs in the HIP library (include/cbs.h)."""
+
+from __future__ import annotations
+
+import dataclasses
+
+import torch
+
+from . import libcbs as L
+
+
+@dataclasses.dataclass
+class SolveStats:
+    status: int
+    iterations: int
+    converged: bool
+    residual: float
+    eps_shift: float
+    ms: float
+
+
+def _stats(rc, st) -> SolveStats:
+    return SolveStats(rc, st.iterations, bool(st.converged), st.residual, st.eps_shift, st.ms)
+
+
+def _require_gpu(t: torch.Tensor, name: str, dtype, shape):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} shape {tuple(t.shape)} != {tuple(shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """A CBS plan on one GPU: grid, optics, absorbing layer, workspace.
+
+    shape = (nx, ny, nz); pml per side in voxels; lengths in metres.  The
+    workspace is a torch uint8 tensor on ``device`` (exactly the bytes
+    cbs_plan_workspace_bytes reports, 256-byte aligned)."""
+
+    def __init__(self, shape, pitch, lambda0=1.064e-6, n_bg=1.0, pml=(0, 0, 0), device=None,
+                 stream: torch.cuda.Stream | None = None, pml_order=2, sigma_max=1.0,
+                 shift_factor=1.1):
+        nx, ny, nz = (int(v) for v in shape)
+        self.shape = (nx, ny, nz)
+        self.pitch, self.lambda0, self.n_bg, self.pml = float(pitch), float(lambda0), float(n_bg), tuple(pml)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        nbytes = L.cbs_plan_workspace_bytes(nx, ny, nz)
+        if nbytes == 0:
+            raise ValueError(f"grid {shape} is not supported by libcbs")
+        self.workspace_bytes = nbytes
+        raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._raw = raw
+        self.workspace = raw[off:off + nbytes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.handle = L.cbs_plan_create(nx, ny, nz, self.pitch, self.lambda0, self.n_bg, self.pml,
+                                        self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if (pml_order, sigma_max) != (2, 1.0):
+            L.cbs_plan_set_pml_profile(self.handle, int(pml_order), float(sigma_max))
+        if shift_factor != 1.1:
+            L.cbs_plan_set_shift_factor(self.handle, float(shift_factor))
+        self._eps_ref = None
+
+    # -- shapes ---------------------------------------------------------------
+    @property
+    def vshape(self):
+        nx, ny, nz = self.shape
+        return (nz, ny, nx)
+
+    @property
+    def fshape(self):
+        return (3,) + self.vshape
+
+    def new_field(self):
+        return torch.zeros(self.fshape, dtype=torch.complex64, device=self.device)
+
+    # -- entry points -----------------------------------------------------------
+    def set_permittivity(self, eps_r: torch.Tensor):
+        dtype = {torch.float32: L.CBS_F32, torch.complex64: L.CBS_C64}.get(eps_r.dtype)
+        if dtype is None:
+            raise ValueError("eps_r must be float32 or complex64")
+        _require_gpu(eps_r, "eps_r", eps_r.dtype, self.vshape)
+        L.cbs_set_permittivity(self.handle, eps_r.data_ptr(), dtype)
+        self._eps_ref = eps_r
+        return self.eps_shift
+
+    @property
+    def eps_shift(self) -> float:
+        return L.cbs_eps_shift(self.handle)
+
+    @staticmethod
+    def _opts(tol, max_iter, check_every, warm=False, scattered=False, history=False):
+        flags = (L.CBS_WARM_START if warm else 0) | (L.CBS_RETURN_SCATTERED if scattered else 0) \
+            | (L.CBS_RECORD_HISTORY if history else 0)
+        return L.cbs_opts(float(tol), int(max_iter), int(check_every), flags)
+
+    def solve(self, E: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
+              warm=False, scattered=False, history=False, pol=None, field=None, point=None,
+              kind=None):
+        """Forward solve (plane wave by default).  Returns (E, SolveStats)."""
+        if E is None:
+            E = self.new_field()
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        src = L.cbs_source()
+        if field is not None:
+            _require_gpu(field, "field", torch.complex64, self.fshape)
+            src.kind = L.CBS_SRC_FIELD
+            src.field = field.data_ptr()
+        elif point is not None:
+            r0, amp = point
+            src.kind = L.CBS_SRC_POINT
+            for c in range(3):
+                src.r0[c] = int(r0[c])
+                a = complex(amp[c])
+                src.amp[c][0], src.amp[c][1] = a.real, a.imag
+        else:
+            src.kind = L.CBS_SRC_PLANE_WAVE if kind is None else kind
+            if pol is not None:
+                for c in range(3):
+                    a = complex(pol[c])
+                    src.pol[c][0], src.pol[c][1] = a.real, a.imag
+        rc, st = L.cbs_solve(self.handle, src, E.data_ptr(),
+                             self._opts(tol, max_iter, check_every, warm, scattered, history))
+        return E, _stats(rc, st)
+
+    def adjoint(self, E_fwd: torch.Tensor | None = None, r0=None, amp=None, field=None,
+                E_adj: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
+                warm=False, history=False):
+        """Adjoint solve.  With r0 and E_fwd: source conj(E_fwd(r0)) at r0
+        (objective |E(r0)|^2).  With r0 and amp: that amplitude.  With field:
+        a general source.  Returns (E_adj, SolveStats)."""
+        if E_adj is None:
+            E_adj = self.new_field()
+        _require_gpu(E_adj, "E_adj", torch.complex64, self.fshape)
+        src = L.cbs_source()
+        fptr = 0
+        if field is not None:
+            _require_gpu(field, "field", torch.complex64, self.fshape)
+            src.kind = L.CBS_SRC_FIELD
+            src.field = field.data_ptr()
+        else:
+            src.kind = L.CBS_SRC_POINT
+            for c in range(3):
+                src.r0[c] = int(r0[c])
+            if amp is not None:
+                for c in range(3):
+                    a = complex(amp[c])
+                    src.amp[c][0], src.amp[c][1] = a.real, a.imag
+            else:
+                _require_gpu(E_fwd, "E_fwd", torch.complex64, self.fshape)
+                fptr = E_fwd.data_ptr()
+        rc, st = L.cbs_adjoint_solve(self.handle, fptr, src, E_adj.data_ptr(),
+                                     self._opts(tol, max_iter, check_every, warm, False, history))
+        return E_adj, _stats(rc, st)
+
+    def gradient(self, E: torch.Tensor, E_adj: torch.Tensor, box_lo=None, box_hi=None,
+                 scale=2.0, out: torch.Tensor | None = None):
+        """scale * k0^2 * Re(sum_c E_adj,c E_c) over [box_lo, box_hi) -> [z, y, x] float32."""
+        nx, ny, nz = self.shape
+        lo = tuple(box_lo) if box_lo is not None else (0, 0, 0)
+        hi = tuple(box_hi) if box_hi is not None else (nx, ny, nz)
+        bshape = (hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0])
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        _require_gpu(E_adj, "E_adj", torch.complex64, self.fshape)
+        if out is None:
+            out = torch.empty(bshape, dtype=torch.float32, device=self.device)
+        _require_gpu(out, "out", torch.float32, bshape)
+        L.cbs_gradient(self.handle, E.data_ptr(), E_adj.data_ptr(), lo, hi, scale, out.data_ptr())
+        return out
+
+    def apply_green(self, W: torch.Tensor, out: torch.Tensor | None = None):
+        _require_gpu(W, "W", torch.complex64, self.fshape)
+        if out is None:
+            out = self.new_field()
+        L.cbs_apply_green(self.handle, W.data_ptr(), out.data_ptr())
+        return out
+
+    def history(self, n=1 << 16):
+        return L.cbs_history(self.handle, n)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            L.cbs_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

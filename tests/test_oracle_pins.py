@@ -124,18 +124,20 @@ def test_curl_curl_fft_matches_dense():
 # ---------------------------------------------------------------------------
 # CBS reaches the plain definition (dense LU)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("shape,pml,loss,seed", [
-    ((4, 5, 6), (1, 1, 1), 0.0, 1),
-    ((5, 5, 5), (1, 1, 2), 0.3, 2),
-    ((6, 4, 7), (0, 1, 2), 0.0, 3),
-    ((8, 8, 8), (2, 2, 2), 0.1, 4),
+@pytest.mark.parametrize("shape,pml,loss,seed,kappa", [
+    ((4, 5, 6), (1, 1, 1), 0.0, 1, 1.1),
+    ((5, 5, 5), (1, 1, 2), 0.3, 2, 1.1),
+    ((5, 5, 5), (1, 1, 2), 0.3, 2, 1.0),
+    ((6, 4, 7), (0, 1, 2), 0.0, 3, 1.1),
+    ((8, 8, 8), (2, 2, 2), 0.1, 4, 1.1),
+    ((8, 8, 8), (2, 2, 2), 0.1, 4, 1.0),
 ])
-def test_cbs_converges_to_dense_solution(shape, pml, loss, seed):
-    """CBS reaches A^-1 S on every voxel where gamma != 0.  Where the absorbing
-    potential sits exactly on the shift's bound (V0 = i eps, so V = 0 and
-    gamma = 0) the iteration never updates the voxel, which keeps E^(0) = 0;
-    because V = 0 there, such voxels feed nothing back into the rest."""
-    g = small_grid(shape, pml=pml)
+def test_cbs_converges_to_dense_solution(shape, pml, loss, seed, kappa):
+    """CBS reaches A^-1 S on every voxel where gamma != 0.  With eps exactly
+    max|V0| (kappa = 1), voxels where the absorbing potential sits on the
+    bound (V0 = i eps, so V = 0 and gamma = 0) are never updated and keep
+    E^(0) = 0; because V = 0 there, they feed nothing back into the rest."""
+    g = small_grid(shape, pml=pml, shift_factor=kappa)
     eps = scenes.random_passive_eps(shape, pml, seed, loss=loss)
     S = oc.plane_wave_source(g, eps)
     ref = dense.dense_solve(g, eps, S)
@@ -147,6 +149,8 @@ def test_cbs_converges_to_dense_solution(shape, pml, loss, seed):
     live = np.broadcast_to(~stuck, res.E_s.shape)
     assert rel(res.E_s[live], ref[live]) < 1e-9
     assert np.all(res.E_s[~live] == 0)
+    if kappa > 1:
+        assert live.all()
 
 
 @pytest.mark.parametrize("shape,pml,seed", [((5, 5, 5), (1, 1, 2), 2), ((6, 5, 4), (1, 2, 1), 6)])
