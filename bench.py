@@ -1,0 +1,235 @@
+"""Benchmark of the CBS hot path on one MI355X.
+
+A step is one optimisation step of the 621 x 621 x 261 design volume (177 nm
+pitch, zone-plate lens D = 100 um, NA 0.84, n = 1.45, lambda0 = 1064 nm):
+set the permittivity, forward CBS solve of the x-polarised plane wave to
+tol, adjoint CBS solve for the focal intensity |E(r0)|^2 to tol, and the
+permittivity gradient over the 2 um design slab.  Inputs are resident in HBM
+before the timed region.  value = voxels x CBS iterations / second.
+
+Prints one JSON line (rank 0) with the per-kernel roofline of the dominant
+pass (HIP events on the plan's stream) and the FP64 CPU oracle timed on a
+bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CBS Gvoxel-iter/s (vector c64) + % HBM peak; p50/p99 served solve latency"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per voxel per launch of each pass (complex64, 3 comps):
+#   y/z passes read and write the 24 B field; the x pass reads GW, E_s (24 B
+#   each) and V0 (8 B) and writes E_s and the next W (24 B each).
+PASS_BYTES = {"ky_forward": 48, "kz_green": 48, "ky_inverse": 48, "kx_update": 104}
+ITER_BYTES = 248
+PASS_SOURCES = ["paper_2506_15411_amd/csrc/kernels.hpp", "paper_2506_15411_amd/csrc/codelets.hpp"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in PASS_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from paper_2506_15411_amd import scenes
+    if name == "zoneplate100":
+        return scenes.zoneplate100_design(0)
+    if name == "zoneplate16":
+        return scenes.zoneplate16_design(0)
+    if name == "sphere64":
+        sc = scenes.sphere64()
+        import dataclasses
+        return dataclasses.replace(sc, r0=(32, 32, 48), design_box=((8, 8, 16), (56, 56, 48)))
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_from_profile(name: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def copy_probe(dev, nbytes=1 << 30, reps=1):
+    """Plain streaming copy of nbytes (read + write) in the library's probe kernel."""
+    import torch
+    from paper_2506_15411_amd import libcbs as L
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = L.cbs_bandwidth_probe(src.data_ptr(), dst.data_ptr(), nbytes, reps,
+                               torch.cuda.current_stream(dev).cuda_stream)
+    del src, dst
+    return ms
+
+
+def cpu_baseline(sc):
+    """FP64 oracle on the host: one CBS iteration of the same workload.
+
+    The oracle's own setup (potentials) is timed separately and subtracted
+    from one oracle call with max_iter = 1."""
+    from oracle import cbs as oc
+    g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
+    eps = sc.eps_r
+    S = oc.plane_wave_source(g, eps)
+    t0 = time.perf_counter()
+    pot = oc.potentials(g, eps)
+    t1 = time.perf_counter()
+    del pot
+    t2 = time.perf_counter()
+    r = oc.cbs(g, eps, S, tol=0.0, max_iter=1)
+    t3 = time.perf_counter()
+    del r, S
+    per_it = (t3 - t2) - (t1 - t0)
+    return {
+        "value": round(sc.n_vox / per_it / 1e9, 6),
+        "unit": "Gvoxel-iter/s",
+        "cores": oc._WORKERS,
+        "kind": "oracle",
+        "sample": (f"one FP64 oracle CBS iteration on the full {sc.shape[0]}x{sc.shape[1]}x"
+                   f"{sc.shape[2]} volume: {per_it:.1f} s (oracle setup, {t1 - t0:.1f} s, "
+                   f"timed separately and excluded)"),
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="zoneplate100",
+                    choices=["zoneplate100", "zoneplate16", "sphere64"])
+    ap.add_argument("--tol", type=float, default=1e-4)
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--check-every", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="profiling mode: run this many CBS iterations of the workload "
+                         "(one launch of each pass per iteration) and a 1 GiB device copy "
+                         "used to calibrate memory counters; prints no JSON line")
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the CBS solver of this package is a "
+              "single-GPU path (no multi-GPU decomposition is built); use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2506_15411_amd.solver import Plan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    dev = torch.device("cuda:0")
+    log(f"[bench] building scene {args.workload}")
+    sc = workload(args.workload)
+    eps = torch.from_numpy(sc.eps_r).to(dev)
+    plan = Plan(sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml, device=dev)
+    E = plan.new_field()
+    Ea = plan.new_field()
+    lo, hi = sc.design_box
+    grad = torch.empty((hi[2] - lo[2], hi[1] - lo[1], hi[0] - lo[0]), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+
+    if args.profile_iters > 0:
+        plan.set_permittivity(eps)
+        passes = plan.time_passes(iters=args.profile_iters, E=E)
+        ms = copy_probe(dev)
+        log(f"[bench] profile mode: {args.profile_iters} iterations of {sc.name}; "
+            f"passes (ms) {passes}; copy probe 1 GiB: {ms:.4f} ms = {2 * 2**30 / ms / 1e6:.0f} GB/s")
+        return 0
+
+    def step():
+        plan.set_permittivity(eps)
+        _, s1 = plan.solve(E, tol=args.tol, max_iter=args.max_iter, check_every=args.check_every)
+        _, s2 = plan.adjoint(E_fwd=E, r0=sc.r0, E_adj=Ea, tol=args.tol, max_iter=args.max_iter,
+                             check_every=args.check_every)
+        plan.gradient(E, Ea, lo, hi, scale=2.0, out=grad)
+        return s1, s2
+
+    for i in range(args.warmup):
+        s1, s2 = step()
+        log(f"[bench] warmup {i}: fwd {s1.iterations} it ({s1.ms:.0f} ms, eta {s1.residual:.2e}), "
+            f"adj {s2.iterations} it ({s2.ms:.0f} ms, eta {s2.residual:.2e})")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    solve_ms = 0.0
+    for i in range(args.steps):
+        s1, s2 = step()
+        iters += s1.iterations + s2.iterations
+        solve_ms += s1.ms + s2.ms
+        log(f"[bench] step {i}: fwd {s1.iterations} it, adj {s2.iterations} it")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nvox = sc.n_vox
+    value = nvox * iters / dt / 1e9
+    iter_rate = nvox * iters / (solve_ms / 1e3) / 1e9
+
+    # per-pass device time (HIP events on the plan's stream)
+    passes = plan.time_passes(iters=10)
+    log(f"[bench] passes (ms): {passes}")
+    dom = max(PASS_BYTES, key=lambda k: passes[k])
+    achieved = PASS_BYTES[dom] * nvox / (passes[dom] * 1e-3) / 1e9
+    traffic = traffic_from_profile(args.workload, dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": dom,
+                "alg_bytes_per_launch": PASS_BYTES[dom] * nvox,
+                "avg_launch_ms": round(passes[dom], 4)}
+    it_ms = sum(passes.values())
+    copy_ms = copy_probe(dev, reps=5)
+    copy_gbs = 2 * (1 << 30) / (copy_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gvoxel-iter/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3 / args.steps, 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{sc.name} {sc.shape[0]}x{sc.shape[1]}x{sc.shape[2]} "
+                               f"pitch {sc.pitch * 1e9:.1f} nm: forward + adjoint CBS (tol "
+                               f"{args.tol:g}) + gradient over the design slab",
+                   "voxels": nvox, "iterations_per_step": iters / args.steps,
+                   "tol": args.tol, "shift_factor": 1.1, "pml_per_side": list(sc.pml)},
+        "hbm_frac_iteration": round(ITER_BYTES * nvox / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "iteration_ms": round(it_ms, 3),
+        "solve_only_gvoxel_iter_s": round(iter_rate, 3),
+        "passes_ms": {k: round(v, 4) for k, v in passes.items()},
+        "copy_probe_gbs": round(copy_gbs, 1),
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        del E, Ea, plan
+        torch.cuda.empty_cache()
+        log("[bench] timing the FP64 oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(sc)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

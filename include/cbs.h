@@ -172,6 +172,21 @@ int cbs_apply_green(cbs_plan_t plan, const void* in_dev, void* out_dev);
  * error. */
 int cbs_history(cbs_plan_t plan, double* out_host, int max);
 
+/* Measurement aid: run a cold-start plane-wave solve of exactly `iters`
+ * iterations (no early stop) into E_dev, with HIP events recorded on the
+ * plan's stream between the passes, and return the mean device time per
+ * launch in ms_out[0..4] = { y forward, z (forward + Green + inverse),
+ * y inverse, x (inverse + update + forward), residual }.  Synchronises. */
+int cbs_time_passes(cbs_plan_t plan, void* E_dev, int iters, float* ms_out);
+
+/* Measurement aid (no plan needed): copy `bytes` (a multiple of 16) from
+ * src_dev to dst_dev `reps` times with a plain streaming copy kernel on
+ * `stream` and return the mean device ms per copy in *ms_out.  Used as the
+ * achievable-bandwidth reference and to calibrate memory counters.
+ * Synchronises the stream. */
+int cbs_bandwidth_probe(const void* src_dev, void* dst_dev, size_t bytes, int reps,
+                        void* stream, float* ms_out);
+
 /* eps (1/m^2) of the current medium, or a negative value if none is set. */
 double cbs_eps_shift(cbs_plan_t plan);
 

@@ -50,7 +50,7 @@ import os
 import numpy as np
 import scipy.fft as sfft
 
-_WORKERS = max(1, os.cpu_count() or 1)
+_WORKERS = max(1, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
 
 
 # ---------------------------------------------------------------------------

@@ -264,6 +264,15 @@ __global__ void k_gradient(const float2* E, const float2* Ea, long long sE, int 
   }
 }
 
+// streaming copy: one float4 per thread over a grid that covers the buffer
+// (the fastest plain copy form measured on this part)
+constexpr int kCopyThreads = 256;
+__global__ void __launch_bounds__(kCopyThreads)
+k_copy(const float4* __restrict__ src, float4* __restrict__ dst, long long n4) {
+  const long long i = (long long)blockIdx.x * kCopyThreads + threadIdx.x;
+  if (i < n4) dst[i] = src[i];
+}
+
 }  // namespace cbs
 
 using namespace cbs;
@@ -289,6 +298,7 @@ struct cbs_plan_s {
   double eps;  // 1/m^2
   int hist_len;
   hipEvent_t ev0, ev1;
+  hipEvent_t evp[6];
 };
 
 namespace {
@@ -583,12 +593,19 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
     const double ang = p->kb * pitch_m * k;
     ph[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
   }
+  // events are created null and destroyed by cleanup whatever succeeded
   auto cleanup = [&](int rc) {
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    for (int i = 0; i < 6; ++i)
+      if (p->evp[i]) (void)hipEventDestroy(p->evp[i]);
     delete p;
     return rc;
   };
   if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
     return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
+  for (int i = 0; i < 6; ++i)
+    if (hipEventCreate(&p->evp[i]) != hipSuccess) return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
   hipError_t e = hipSuccess;
   e = e == hipSuccess ? hipMemcpyAsync(p->twx, tx.data(), nx * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
   e = e == hipSuccess ? hipMemcpyAsync(p->twy, ty.data(), ny * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
@@ -597,11 +614,7 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
   e = e == hipSuccess ? hipMemsetAsync(p->W, 0, L.V0 - L.W, p->stream) : e;
   e = e == hipSuccess ? hipMemsetAsync(p->state, 0, sizeof(DevState), p->stream) : e;
   e = e == hipSuccess ? hipStreamSynchronize(p->stream) : e;
-  if (e != hipSuccess) {
-    hipEventDestroy(p->ev0);
-    hipEventDestroy(p->ev1);
-    return cleanup(fail(CBS_E_HIP, "plan upload: %s", hipGetErrorString(e)));
-  }
+  if (e != hipSuccess) return cleanup(fail(CBS_E_HIP, "plan upload: %s", hipGetErrorString(e)));
   *out = p;
   return CBS_OK;
 }
@@ -782,6 +795,73 @@ int cbs_apply_green(cbs_plan_t p, const void* in, void* out) {
   return CBS_OK;
 }
 
+int cbs_time_passes(cbs_plan_t p, void* E_dev, int iters, float* ms_out) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if (!E_dev || !ms_out || iters < 1) return fail(CBS_E_INVALID, "bad arguments");
+  CbsArgs a = base_args(p);
+  float2 pol[3];
+  if ((rc = set_source(p, a, nullptr, false, pol))) return rc;
+  a.E = static_cast<float2*>(E_dev);
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, 0.0, iters, 0);
+  HIP_LAUNCHED();
+  p->ox->k1(a, K1_FWD, p->stream);
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int it = 0; it < iters; ++it) {
+    HIP_TRY(hipEventRecord(p->evp[0], p->stream));
+    p->oy->ky(a, -1, p->stream);
+    HIP_TRY(hipEventRecord(p->evp[1], p->stream));
+    p->oz->kz(a, p->stream);
+    HIP_TRY(hipEventRecord(p->evp[2], p->stream));
+    p->oy->ky(a, +1, p->stream);
+    HIP_TRY(hipEventRecord(p->evp[3], p->stream));
+    p->ox->k1(a, K1_ITER, p->stream);
+    HIP_TRY(hipEventRecord(p->evp[4], p->stream));
+    hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
+                       p->k1_blocks, p->state, p->hist);
+    HIP_LAUNCHED();
+    HIP_TRY(hipEventRecord(p->evp[5], p->stream));
+    HIP_TRY(hipEventSynchronize(p->evp[5]));
+    for (int k = 0; k < 5; ++k) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, p->evp[k], p->evp[k + 1]));
+      acc[k] += ms;
+    }
+  }
+  for (int k = 0; k < 5; ++k) ms_out[k] = (float)(acc[k] / iters);
+  return CBS_OK;
+}
+
+int cbs_bandwidth_probe(const void* src, void* dst, size_t bytes, int reps, void* stream,
+                        float* ms_out) {
+  if (!src || !dst || !ms_out || reps < 1 || bytes == 0 || bytes % 16 != 0)
+    return fail(CBS_E_INVALID, "bandwidth probe: bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const long long n4 = (long long)(bytes / 16);
+  const long long nb = (n4 + kCopyThreads - 1) / kCopyThreads;
+  if (nb > 0x7fffffffLL) return fail(CBS_E_INVALID, "bandwidth probe: buffer too large");
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = CBS_OK;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kCopyThreads), 0, s,
+                     static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
+  if (hipEventRecord(e0, s) != hipSuccess) rc = fail(CBS_E_HIP, "hipEventRecord failed");
+  for (int r = 0; r < reps && rc == CBS_OK; ++r)
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(kCopyThreads), 0, s,
+                       static_cast<const float4*>(src), static_cast<float4*>(dst), n4);
+  hipError_t e = hipGetLastError();
+  if (rc == CBS_OK && e != hipSuccess) rc = fail(CBS_E_HIP, "kernel launch: %s", hipGetErrorString(e));
+  if (rc == CBS_OK && hipEventRecord(e1, s) != hipSuccess) rc = fail(CBS_E_HIP, "hipEventRecord failed");
+  if (rc == CBS_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(CBS_E_HIP, "hipEventSynchronize failed");
+  float ms = 0.f;
+  if (rc == CBS_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(CBS_E_HIP, "hipEventElapsedTime failed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc == CBS_OK) *ms_out = ms / reps;
+  return rc;
+}
+
 int cbs_history(cbs_plan_t p, double* out, int max) {
   int rc = check_plan(p, false);
   if (rc) return rc;
@@ -793,8 +873,9 @@ int cbs_history(cbs_plan_t p, double* out, int max) {
 
 int cbs_plan_destroy(cbs_plan_t p) {
   if (!p) return CBS_OK;
-  hipEventDestroy(p->ev0);
-  hipEventDestroy(p->ev1);
+  (void)hipEventDestroy(p->ev0);
+  (void)hipEventDestroy(p->ev1);
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(p->evp[i]);
   delete p;
   return CBS_OK;
 }

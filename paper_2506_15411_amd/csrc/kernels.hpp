@@ -119,6 +119,18 @@ __device__ __forceinline__ float freq_of(int k, int n, float pf, bool& nyq) {
   return pf * float(m);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b mod 8), and each XCD has its own L2.  The y and z passes read 64-byte
+// column tiles, half a 128-byte L2 line; remapping the linear block index so
+// that each XCD walks a contiguous range of tiles puts both halves of a line
+// in the same L2 at about the same time.  Bijective for any block count.
+constexpr int kXcds = 8;
+__device__ __forceinline__ long long xcd_remap(long long b, long long total) {
+  const long long q = total / kXcds, r = total % kXcds;
+  const long long k = b % kXcds, j = b / kXcds;
+  return k * q + (k < r ? k : r) + j;
+}
+
 // ---------------------------------------------------------------------------
 // block reduction of two doubles (residual partials)
 // ---------------------------------------------------------------------------
@@ -231,8 +243,12 @@ k1_xpass(CbsArgs a) {
         sd += (double)(d.x * d.x + d.y * d.y);
         se += (double)(e.x * e.x + e.y * e.y);
         a.E[ebase + x] = e;
+      } else if (a.warm) {
+        e = a.E[ebase + x];
       } else {
-        e = a.warm ? a.E[ebase + x] : make_float2(0.f, 0.f);
+        // cold start: E_s^(0) = 0, whatever the output buffer held
+        e = make_float2(0.f, 0.f);
+        if (!a.green_in) a.E[ebase + x] = e;
       }
       float2 w;
       if (MODE == K1_FWD && a.green_in) {
@@ -288,9 +304,13 @@ ky_pass(CbsArgs a) {
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
   const int xi = tid % TX;
   const int t = tid / TX;
-  const int x = blockIdx.x * TX + xi;
+  const int gx = (a.nx + TX - 1) / TX;
+  const long long L = xcd_remap(blockIdx.x, (long long)gx * a.nz * 3);
+  const int bx = (int)(L % gx);
+  const long long rest = L / gx;
+  const int z = (int)(rest % a.nz), c = (int)(rest / a.nz);
+  const int x = bx * TX + xi;
   const bool xok = x < a.nx;
-  const int z = blockIdx.y, c = blockIdx.z;
   float2* col = a.W + c * a.sW + (long long)z * a.ny * a.nxp + (xok ? x : 0);
   const long long ps = a.nxp;
   __syncthreads();
@@ -335,9 +355,12 @@ kz_pass(CbsArgs a) {
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
   const int xi = tid % TX;
   const int t = tid / TX;
-  const int x = blockIdx.x * TX + xi;
+  const int gx = (a.nx + TX - 1) / TX;
+  const long long L = xcd_remap(blockIdx.x, (long long)gx * a.ny);
+  const int bx = (int)(L % gx);
+  const int y = (int)(L / gx);
+  const int x = bx * TX + xi;
   const bool xok = x < a.nx;
-  const int y = blockIdx.y;
   const long long plane = (long long)a.ny * a.nxp;
   float2* colbase = a.W + (long long)y * a.nxp + (xok ? x : 0);
   __syncthreads();
@@ -395,10 +418,10 @@ kz_pass(CbsArgs a) {
       const float p2 = pxy2 + pz * pz;
       // a = invN / (p2 - kb2 - i eps), b = 1 / (p2 - |pt|^2 - kb2 - i eps)
       const float r1 = p2 - a.kb2;
-      const float s1 = a.invN / (r1 * r1 + e2);
+      const float s1 = a.invN * __builtin_amdgcn_rcpf(r1 * r1 + e2);
       const float2 ga = make_float2(r1 * s1, eps * s1);
       const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
-      const float s2 = 1.0f / (r2 * r2 + e2);
+      const float s2 = __builtin_amdgcn_rcpf(r2 * r2 + e2);
       const float2 gb = make_float2(r2 * s2, eps * s2);
       const float2 u0 = v0[k2], u1 = v1[k2], u2 = v2[k2];
       const float2 sp = make_float2(ptx * u0.x + pty * u1.x + ptz * u2.x,
@@ -471,7 +494,7 @@ void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
 template <int N1, int N2>
 void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
   using G = YGeom<N1, N2, kTY>;
-  dim3 grid((a.nx + kTY - 1) / kTY, a.nz, 3);
+  dim3 grid((unsigned)((long long)((a.nx + kTY - 1) / kTY) * a.nz * 3));
   if (sign < 0)
     hipLaunchKernelGGL((ky_pass<N1, N2, kTY, -1>), grid, dim3(G::THREADS), 0, s, a);
   else
@@ -481,7 +504,7 @@ void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
 template <int N1, int N2>
 void launch_kz(const CbsArgs& a, hipStream_t s) {
   using G = ZGeom<N1, N2, kTZ>;
-  dim3 grid((a.nx + kTZ - 1) / kTZ, a.ny, 1);
+  dim3 grid((unsigned)((long long)((a.nx + kTZ - 1) / kTZ) * a.ny));
   hipLaunchKernelGGL((kz_pass<N1, N2, kTZ>), grid, dim3(G::THREADS), 0, s, a);
 }
 

@@ -64,7 +64,7 @@ _lib = None
 SYMBOLS = [
     "cbs_plan_workspace_bytes", "cbs_axis_supported", "cbs_plan_create",
     "cbs_plan_set_pml_profile", "cbs_plan_set_shift_factor", "cbs_set_permittivity", "cbs_solve", "cbs_adjoint_solve",
-    "cbs_gradient", "cbs_apply_green", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
+    "cbs_gradient", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
     "cbs_last_error",
 ]
 
@@ -103,6 +103,11 @@ def load(path: str | None = None):
     lib.cbs_gradient.restype = c_int
     lib.cbs_apply_green.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.cbs_apply_green.restype = c_int
+    lib.cbs_time_passes.argtypes = [c_void_p, c_void_p, c_int, P(ctypes.c_float)]
+    lib.cbs_time_passes.restype = c_int
+    lib.cbs_bandwidth_probe.argtypes = [c_void_p, c_void_p, c_size_t, c_int, c_void_p,
+                                        P(ctypes.c_float)]
+    lib.cbs_bandwidth_probe.restype = c_int
     lib.cbs_history.argtypes = [c_void_p, P(c_double), c_int]
     lib.cbs_history.restype = c_int
     lib.cbs_eps_shift.argtypes = [c_void_p]
@@ -183,6 +188,19 @@ def cbs_gradient(plan, E_ptr, E_adj_ptr, box_lo, box_hi, scale, grad_ptr):
 
 def cbs_apply_green(plan, in_ptr, out_ptr):
     return check(load().cbs_apply_green(plan, ctypes.c_void_p(in_ptr), ctypes.c_void_p(out_ptr)))
+
+
+def cbs_time_passes(plan, E_ptr, iters):
+    ms = (ctypes.c_float * 5)()
+    check(load().cbs_time_passes(plan, ctypes.c_void_p(E_ptr), int(iters), ms))
+    return [float(v) for v in ms]
+
+
+def cbs_bandwidth_probe(src_ptr, dst_ptr, nbytes, reps, stream_ptr) -> float:
+    ms = ctypes.c_float()
+    check(load().cbs_bandwidth_probe(ctypes.c_void_p(src_ptr), ctypes.c_void_p(dst_ptr), int(nbytes),
+                                     int(reps), ctypes.c_void_p(stream_ptr), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def cbs_history(plan, max_n: int):

@@ -180,6 +180,15 @@ class Plan:
         L.cbs_apply_green(self.handle, W.data_ptr(), out.data_ptr())
         return out
 
+    PASSES = ("ky_forward", "kz_green", "ky_inverse", "kx_update", "residual")
+
+    def time_passes(self, iters=10, E: torch.Tensor | None = None):
+        """Mean device ms per launch of each pass over `iters` iterations."""
+        if E is None:
+            E = self.new_field()
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        return dict(zip(self.PASSES, L.cbs_time_passes(self.handle, E.data_ptr(), iters)))
+
     def history(self, n=1 << 16):
         return L.cbs_history(self.handle, n)
 

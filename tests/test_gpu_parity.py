@@ -164,6 +164,13 @@ def test_repeat_is_bitwise_identical(device):
     E1, s1 = p.solve(tol=0.0, max_iter=30)
     E2, s2 = p.solve(tol=0.0, max_iter=30)
     assert torch.equal(E1, E2) and s1.residual == s2.residual
+    # a cold start ignores what the output buffer holds
+    E3 = torch.full_like(E1, 3.0 - 1.0j)
+    E3, s3 = p.solve(E3, tol=0.0, max_iter=30)
+    assert torch.equal(E1, E3) and s3.residual == s1.residual
+    Ea1, _ = p.adjoint(E_fwd=E1, r0=(16, 16, 20), tol=0.0, max_iter=10)
+    Ea2, _ = p.adjoint(E_fwd=E1, r0=(16, 16, 20), E_adj=E3.clone(), tol=0.0, max_iter=10)
+    assert torch.equal(Ea1, Ea2)
 
 
 @pytest.mark.parametrize("bad,frag", [("gain", "gain"), ("layer", "absorbing layer"),
