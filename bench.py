@@ -85,6 +85,51 @@ def copy_probe(dev, nbytes=1 << 30, reps=1):
     return ms
 
 
+def serving(dev, n_requests: int, load: float, tol: float):
+    """Served stream of mixed-grid forward/adjoint solves (Poisson arrivals,
+    numpy default_rng(0)): one-at-a-time service time measured first, then the
+    stream at `load` x that service rate, continuous-batched and one at a time."""
+    import dataclasses
+    import numpy as np
+    from paper_2506_15411_amd import scenes
+    from paper_2506_15411_amd.serve import Server, summarize
+    trace = scenes.served_trace(n_requests, 1.0, seed=0)
+    unit_arrivals = [r.arrival for r in trace]
+    srv = Server(dev, max_active=4, tol=tol, max_iter=4000)
+
+    def prog(tag):
+        def f(res, k):
+            if k % 5 == 0 or k == len(trace):
+                log(f"[bench] serving {tag}: {k}/{len(trace)} done (last: {res.shape} {res.kind} "
+                    f"it {res.iterations} {res.latency * 1e3:.0f} ms)")
+        return f
+
+    back_to_back = [dataclasses.replace(r, arrival=0.0) for r in trace]
+    t = time.perf_counter()
+    b2b = srv.run_sequential(back_to_back, progress=prog("one-at-a-time service"))
+    service = (time.perf_counter() - t) / len(trace)
+    per = {}
+    for r in b2b:
+        per.setdefault(str(r.shape), []).append(sum(r.iterations))
+    log(f"[bench] serving iterations per grid: " +
+        ", ".join(f"{k}: median {int(np.median(v))} max {max(v)}" for k, v in per.items()))
+    rate = load / service
+    timed = [dataclasses.replace(r, arrival=a / rate) for r, a in zip(trace, unit_arrivals)]
+    log(f"[bench] serving: mean one-at-a-time service {service * 1e3:.1f} ms, rate {rate:.2f}/s")
+    mixed = summarize(srv.run(timed, progress=prog("continuous batching")))
+    seq = summarize(srv.run_sequential(timed, progress=prog("one at a time")))
+    srv.close()
+    return {
+        "requests": len(trace), "load": load, "arrival_rate_hz": round(rate, 3),
+        "grids": ["64^3 lambda/6", "128^3 lambda/6", "192x192x256 lambda/12", "275x275x315 lambda/16"],
+        "mean_service_s": round(service, 4),
+        "max_iter_per_solve": 4000,
+        "iterations_per_grid": {k: {"median": int(np.median(v)), "max": int(max(v))} for k, v in per.items()},
+        "continuous_batching": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in mixed.items()},
+        "one_at_a_time": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in seq.items()},
+    }
+
+
 def cpu_baseline(sc):
     """FP64 oracle on the host: one CBS iteration of the same workload.
 
@@ -125,6 +170,10 @@ def main(argv=None):
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--check-every", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests in the served mixed-grid stream (0 = skip serving)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="arrival rate as a fraction of the one-at-a-time service rate")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode: run this many CBS iterations of the workload "
                          "(one launch of each pass per iteration) and a 1 GiB device copy "
@@ -220,10 +269,19 @@ def main(argv=None):
         "passes_ms": {k: round(v, 4) for k, v in passes.items()},
         "copy_probe_gbs": round(copy_gbs, 1),
         "roofline": roofline,
+        "serving": None,
         "cpu_baseline": None,
     }
+    if args.serve_requests > 0:
+        del E, Ea, grad
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+        out["serving"] = serving(dev, args.serve_requests, args.serve_load, args.tol)
+        if out["serving"]:
+            out["p50_served_latency_s"] = out["serving"]["continuous_batching"]["p50_latency_s"]
+            out["p99_served_latency_s"] = out["serving"]["continuous_batching"]["p99_latency_s"]
     if not args.no_cpu_baseline:
-        del E, Ea, plan
         torch.cuda.empty_cache()
         log("[bench] timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(sc)

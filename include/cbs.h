@@ -154,6 +154,40 @@ int cbs_solve(cbs_plan_t plan, const cbs_source* src, void* E_dev,
 int cbs_adjoint_solve(cbs_plan_t plan, const void* E_fwd_dev, const cbs_source* adj_src,
                       void* E_adj_dev, const cbs_opts* opts, cbs_stats* stats);
 
+/* ---- asynchronous solves (continuous batching) --------------------------
+ * The blocking cbs_solve / cbs_adjoint_solve are built from these.  A plan
+ * holds at most one solve in progress; solves on distinct plans (each with its
+ * own stream) overlap on the device.  Every call returns without waiting for
+ * the device except cbs_solve_end and cbs_batch_step.
+ *
+ * Begin a forward (adjoint = 0; arguments as cbs_solve) or adjoint (adjoint = 1;
+ * arguments as cbs_adjoint_solve) solve: validates, initialises the device state
+ * and enqueues the prologue. */
+int cbs_solve_begin(cbs_plan_t plan, int adjoint, const void* E_fwd_dev, const cbs_source* src,
+                    void* E_dev, const cbs_opts* opts);
+
+/* Enqueue up to `iters` more iterations (never past opts->max_iter) followed by
+ * an asynchronous copy of the device state; iterations after the device has
+ * stopped return at once.  At most 4 quanta may be outstanding
+ * (CBS_E_STATE beyond that: poll first). */
+int cbs_solve_advance(cbs_plan_t plan, int iters);
+
+/* Retire completed quanta without waiting; *done = 1 once the device has
+ * stopped (converged, max_iter reached or diverged); *outstanding (may be
+ * NULL) receives the number of quanta still in flight. */
+int cbs_solve_poll(cbs_plan_t plan, int* done, int* outstanding);
+
+/* Wait for outstanding quanta, enqueue the final E_inc addition of a plane-wave
+ * solve, fill stats and return the solve's status (CBS_OK, CBS_NOT_CONVERGED or
+ * CBS_E_DIVERGED).  CBS_E_STATE if the device has not stopped yet.  The field is
+ * complete when the plan's stream reaches this point. */
+int cbs_solve_end(cbs_plan_t plan, cbs_stats* stats);
+
+/* Grouped step: enqueue `iters` iterations on every plan (each on its own
+ * stream, so their work overlaps), then wait for all of them; done_out[i] = 1
+ * for plans whose solve has stopped.  Every plan must have a solve begun. */
+int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out);
+
 /* Permittivity gradient over a half-open box [lo, hi) (x, y, z):
  *   grad[z][y][x] = scale * k0^2 * Re(sum_c E_adj,c * E_c)
  * (dK/d eps_r = k0^2; scale = 2 for the adjoint source conj(E(r0)) of

@@ -299,6 +299,23 @@ struct cbs_plan_s {
   int hist_len;
   hipEvent_t ev0, ev1;
   hipEvent_t evp[6];
+  // asynchronous solve in progress (cbs_solve_begin .. cbs_solve_end)
+  struct Active {
+    bool on;        // begun and not ended
+    bool stopped;   // device reported the stop; later launches are no-ops
+    bool plane;     // plane-wave source: E_inc is added at the end
+    unsigned flags;
+    int max_iter;
+    int enqueued;   // iterations enqueued so far
+    int head, count;  // ring of outstanding quanta
+    float ms;       // device time from begin to the quantum that stopped
+    float2 pol[3];
+    CbsArgs args;
+  } act;
+  static constexpr int kRing = 4;
+  hipEvent_t evq[kRing];
+  DevState* mirror;  // pinned host copies of the device state, one per quantum slot
+  DevState last;     // state read at the last completed quantum
 };
 
 namespace {
@@ -408,54 +425,152 @@ int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
   return CBS_OK;
 }
 
-// prologue + iteration loop with device-side stopping and periodic host polls
-int run_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, cbs_stats* stats) {
+// Start a solve: device state, point-source amplitude, optional warm-start
+// conversion to the scattered field, and the prologue (W = V E + S, forward x).
+int begin_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* src,
+                const void* E_fwd, const float2 pol[3]) {
+  auto& A = p->act;
+  if (A.on) return fail(CBS_E_STATE, "a solve is already in progress on this plan");
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, o->tol,
                      o->max_iter, (o->flags & CBS_RECORD_HISTORY) ? 1 : 0);
   HIP_LAUNCHED();
-  return CBS_OK;
-}
-
-int iterate(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, cbs_stats* stats) {
+  if (a.src == SRC_POINT) {
+    const long long idx = ((long long)src->r0[2] * p->ny + src->r0[1]) * p->nx + src->r0[0];
+    hipLaunchKernelGGL(k_point_amp, dim3(1), dim3(64), 0, p->stream, p->state,
+                       static_cast<const float2*>(E_fwd), idx, a.sE, E_fwd ? 1 : 0,
+                       (float)(p->pitch * p->pitch),
+                       make_float2((float)src->amp[0][0], (float)src->amp[0][1]),
+                       make_float2((float)src->amp[1][0], (float)src->amp[1][1]),
+                       make_float2((float)src->amp[2][0], (float)src->amp[2][1]));
+    HIP_LAUNCHED();
+  }
+  const bool plane = a.src == SRC_PLANE;
+  a.warm = (o->flags & CBS_WARM_START) ? 1 : 0;
+  if (a.warm && plane) {
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, a.E, p->phase, p->nx,
+                       p->ny, p->nz, pol[0], pol[1], pol[2], -1.0f);
+    HIP_LAUNCHED();
+  }
   HIP_TRY(hipEventRecord(p->ev0, p->stream));
   p->ox->k1(a, K1_FWD, p->stream);
   HIP_LAUNCHED();
-  DevState hs;
-  int done_iters = 0;
-  bool finished = false;
-  while (done_iters < o->max_iter) {
-    const int q = std::min(o->check_every, o->max_iter - done_iters);
-    for (int i = 0; i < q; ++i) {
-      int rc = enqueue_iteration(p, a);
-      if (rc != CBS_OK) return rc;
-    }
-    done_iters += q;
-    HIP_TRY(hipMemcpyAsync(&hs, p->state, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
-    HIP_TRY(hipStreamSynchronize(p->stream));
-    if (hs.done) {
-      finished = true;
-      break;
-    }
+  A.on = true;
+  A.stopped = false;
+  A.plane = plane;
+  A.flags = o->flags;
+  A.max_iter = o->max_iter;
+  A.enqueued = 0;
+  A.head = A.count = 0;
+  A.ms = 0.f;
+  for (int c = 0; c < 3; ++c) A.pol[c] = pol[c];
+  A.args = a;
+  std::memset(&p->last, 0, sizeof(DevState));
+  return CBS_OK;
+}
+
+// Enqueue up to `iters` iterations and an asynchronous copy of the device
+// state into the next pinned slot; never blocks.
+int advance_solve(cbs_plan_s* p, int iters) {
+  auto& A = p->act;
+  if (!A.on) return fail(CBS_E_STATE, "no solve in progress (cbs_solve_begin first)");
+  if (iters < 1) return fail(CBS_E_INVALID, "iters must be >= 1");
+  if (A.stopped || A.enqueued >= A.max_iter) return CBS_OK;
+  if (A.count == cbs_plan_s::kRing)
+    return fail(CBS_E_STATE, "%d quanta already outstanding; poll before advancing", A.count);
+  const int q = std::min(iters, A.max_iter - A.enqueued);
+  for (int i = 0; i < q; ++i) {
+    int rc = enqueue_iteration(p, A.args);
+    if (rc != CBS_OK) return rc;
   }
-  (void)finished;
-  HIP_TRY(hipEventRecord(p->ev1, p->stream));
-  HIP_TRY(hipEventSynchronize(p->ev1));
-  float ms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-  HIP_TRY(hipMemcpy(&hs, p->state, sizeof(DevState), hipMemcpyDeviceToHost));
-  p->hist_len = (o->flags & CBS_RECORD_HISTORY) ? std::min(hs.iter, kHistCap) : 0;
+  A.enqueued += q;
+  const int slot = (A.head + A.count) % cbs_plan_s::kRing;
+  HIP_TRY(hipMemcpyAsync(&p->mirror[slot], p->state, sizeof(DevState), hipMemcpyDeviceToHost,
+                         p->stream));
+  HIP_TRY(hipEventRecord(p->evq[slot], p->stream));
+  A.count++;
+  return CBS_OK;
+}
+
+// Retire completed quanta in order; never blocks.
+int poll_solve(cbs_plan_s* p, int* done) {
+  auto& A = p->act;
+  if (!A.on) return fail(CBS_E_STATE, "no solve in progress");
+  while (A.count > 0) {
+    const hipError_t e = hipEventQuery(p->evq[A.head]);
+    if (e == hipErrorNotReady) break;
+    if (e != hipSuccess) return fail(CBS_E_HIP, "hipEventQuery: %s", hipGetErrorString(e));
+    p->last = p->mirror[A.head];
+    if (p->last.done && !A.stopped) {
+      A.stopped = true;
+      HIP_TRY(hipEventElapsedTime(&A.ms, p->ev0, p->evq[A.head]));
+    }
+    A.head = (A.head + 1) % cbs_plan_s::kRing;
+    A.count--;
+  }
+  if (done) *done = A.stopped ? 1 : 0;
+  return CBS_OK;
+}
+
+int wait_solve(cbs_plan_s* p) {
+  auto& A = p->act;
+  if (A.count > 0) {
+    const int tail = (A.head + A.count - 1) % cbs_plan_s::kRing;
+    HIP_TRY(hipEventSynchronize(p->evq[tail]));
+  }
+  return poll_solve(p, nullptr);
+}
+
+// Finish: add E_inc for plane-wave solves (enqueued), report stats and status.
+int end_solve(cbs_plan_s* p, cbs_stats* stats) {
+  auto& A = p->act;
+  if (!A.on) return fail(CBS_E_STATE, "no solve in progress");
+  int rc = wait_solve(p);
+  if (rc) return rc;
+  if (!A.stopped) return fail(CBS_E_STATE, "solve has not stopped yet (advance further)");
+  A.on = false;
+  if (A.plane && !(A.flags & CBS_RETURN_SCATTERED)) {
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, A.args.E, p->phase,
+                       p->nx, p->ny, p->nz, A.pol[0], A.pol[1], A.pol[2], 1.0f);
+    HIP_LAUNCHED();
+  }
+  const DevState& hs = p->last;
+  p->hist_len = (A.flags & CBS_RECORD_HISTORY) ? std::min(hs.iter, kHistCap) : 0;
   if (stats) {
     stats->iterations = hs.iter;
     stats->converged = hs.status == 1;
     stats->residual = hs.eta;
     stats->eps_shift = p->eps;
-    stats->ms = ms;
+    stats->ms = A.ms;
   }
   if (hs.status == 3) return fail(CBS_E_DIVERGED, "non-finite residual after %d iterations", hs.iter);
   if (hs.status == 1) return CBS_OK;
   g_err = "max_iter reached before the residual met tol";
   return CBS_NOT_CONVERGED;
 }
+
+// Blocking solve on top of the primitives: host polls every check_every.
+int run_blocking(cbs_plan_s* p, int check_every, cbs_stats* stats) {
+  int done = 0, rc = CBS_OK;
+  while (!done) {
+    if ((rc = advance_solve(p, check_every))) break;
+    if ((rc = wait_solve(p))) break;
+    if ((rc = poll_solve(p, &done))) break;
+  }
+  if (rc) {
+    p->act.on = false;
+    (void)hipStreamSynchronize(p->stream);
+    return rc;
+  }
+  rc = end_solve(p, stats);
+  const hipError_t e = hipStreamSynchronize(p->stream);
+  if (e != hipSuccess) return fail(CBS_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  return rc;
+}
+
+// Argument checks and source set-up shared by the blocking and the
+// asynchronous entry points.
+int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cbs_opts* o,
+            CbsArgs& a, float2 pol[3]);
 
 int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, float2 pol[3]) {
   const int kind = src ? src->kind : CBS_SRC_PLANE_WAVE;
@@ -499,6 +614,23 @@ int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, f
   a.pol[0] = pol[0];
   a.pol[1] = pol[1];
   a.pol[2] = pol[2];
+  return CBS_OK;
+}
+
+int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cbs_opts* o,
+            CbsArgs& a, float2 pol[3]) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!E) return fail(CBS_E_INVALID, "output field is NULL");
+  if (adjoint) {
+    if (!src) return fail(CBS_E_INVALID, "adjoint source is NULL");
+    if (src->kind != CBS_SRC_POINT && src->kind != CBS_SRC_FIELD)
+      return fail(CBS_E_INVALID, "adjoint source must be POINT or FIELD");
+  }
+  a = base_args(p);
+  if ((rc = set_source(p, a, src, adjoint != 0, pol))) return rc;
+  a.E = static_cast<float2*>(E);
   return CBS_OK;
 }
 
@@ -599,6 +731,9 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
     if (p->ev1) (void)hipEventDestroy(p->ev1);
     for (int i = 0; i < 6; ++i)
       if (p->evp[i]) (void)hipEventDestroy(p->evp[i]);
+    for (int i = 0; i < cbs_plan_s::kRing; ++i)
+      if (p->evq[i]) (void)hipEventDestroy(p->evq[i]);
+    if (p->mirror) (void)hipHostFree(p->mirror);
     delete p;
     return rc;
   };
@@ -606,6 +741,10 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
     return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
   for (int i = 0; i < 6; ++i)
     if (hipEventCreate(&p->evp[i]) != hipSuccess) return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
+  for (int i = 0; i < cbs_plan_s::kRing; ++i)
+    if (hipEventCreate(&p->evq[i]) != hipSuccess) return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
+  if (hipHostMalloc((void**)&p->mirror, cbs_plan_s::kRing * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(CBS_E_HIP, "hipHostMalloc of the state mirror failed"));
   hipError_t e = hipSuccess;
   e = e == hipSuccess ? hipMemcpyAsync(p->twx, tx.data(), nx * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
   e = e == hipSuccess ? hipMemcpyAsync(p->twy, ty.data(), ny * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
@@ -691,69 +830,72 @@ double cbs_eps_shift(cbs_plan_t p) { return (p && p->have_eps) ? p->eps : -1.0; 
 
 int cbs_solve(cbs_plan_t p, const cbs_source* src, void* E_dev, const cbs_opts* o,
               cbs_stats* stats) {
-  int rc = check_plan(p, true);
-  if (rc) return rc;
-  if ((rc = check_opts(o))) return rc;
-  if (!E_dev) return fail(CBS_E_INVALID, "E is NULL");
-  CbsArgs a = base_args(p);
+  CbsArgs a;
   float2 pol[3];
-  if ((rc = set_source(p, a, src, false, pol))) return rc;
-  a.E = static_cast<float2*>(E_dev);
-  const bool plane = a.src == SRC_PLANE;
-  const bool warm = (o->flags & CBS_WARM_START) != 0;
-  if ((rc = run_solve(p, a, o, stats))) return rc;
-  if (a.src == SRC_POINT) {
-    hipLaunchKernelGGL(k_point_amp, dim3(1), dim3(64), 0, p->stream, p->state,
-                       (const float2*)nullptr, 0LL, a.sE, 0, (float)(p->pitch * p->pitch),
-                       make_float2((float)src->amp[0][0], (float)src->amp[0][1]),
-                       make_float2((float)src->amp[1][0], (float)src->amp[1][1]),
-                       make_float2((float)src->amp[2][0], (float)src->amp[2][1]));
-    HIP_LAUNCHED();
-  }
-  const int gb = 2048, tb = 256;
-  if (warm && plane) {
-    hipLaunchKernelGGL(k_incident, dim3(gb), dim3(tb), 0, p->stream, a.E, p->phase, p->nx,
-                       p->ny, p->nz, pol[0], pol[1], pol[2], -1.0f);
-    HIP_LAUNCHED();
-  }
-  a.warm = warm ? 1 : 0;
-  rc = iterate(p, a, o, stats);
-  if (rc < 0) return rc;
-  if (plane && !(o->flags & CBS_RETURN_SCATTERED)) {
-    hipLaunchKernelGGL(k_incident, dim3(gb), dim3(tb), 0, p->stream, a.E, p->phase, p->nx,
-                       p->ny, p->nz, pol[0], pol[1], pol[2], 1.0f);
-    HIP_LAUNCHED();
-    HIP_TRY(hipStreamSynchronize(p->stream));
-  }
-  return rc;
+  int rc = prepare(p, 0, src, E_dev, o, a, pol);
+  if (rc) return rc;
+  if ((rc = begin_solve(p, a, o, src, nullptr, pol))) return rc;
+  return run_blocking(p, o->check_every, stats);
 }
 
 int cbs_adjoint_solve(cbs_plan_t p, const void* E_fwd, const cbs_source* adj, void* E_adj,
                       const cbs_opts* o, cbs_stats* stats) {
+  CbsArgs a;
+  float2 pol[3];
+  int rc = prepare(p, 1, adj, E_adj, o, a, pol);
+  if (rc) return rc;
+  if ((rc = begin_solve(p, a, o, adj, E_fwd, pol))) return rc;
+  return run_blocking(p, o->check_every, stats);
+}
+
+int cbs_solve_begin(cbs_plan_t p, int adjoint, const void* E_fwd, const cbs_source* src,
+                    void* E_dev, const cbs_opts* o) {
+  CbsArgs a;
+  float2 pol[3];
+  int rc = prepare(p, adjoint, src, E_dev, o, a, pol);
+  if (rc) return rc;
+  return begin_solve(p, a, o, src, adjoint ? E_fwd : nullptr, pol);
+}
+
+int cbs_solve_advance(cbs_plan_t p, int iters) {
   int rc = check_plan(p, true);
   if (rc) return rc;
-  if ((rc = check_opts(o))) return rc;
-  if (!E_adj) return fail(CBS_E_INVALID, "E_adj is NULL");
-  if (!adj) return fail(CBS_E_INVALID, "adjoint source is NULL");
-  if (adj->kind != CBS_SRC_POINT && adj->kind != CBS_SRC_FIELD)
-    return fail(CBS_E_INVALID, "adjoint source must be POINT or FIELD");
-  CbsArgs a = base_args(p);
-  float2 pol[3];
-  if ((rc = set_source(p, a, adj, true, pol))) return rc;
-  a.E = static_cast<float2*>(E_adj);
-  a.warm = (o->flags & CBS_WARM_START) ? 1 : 0;
-  if ((rc = run_solve(p, a, o, stats))) return rc;
-  if (a.src == SRC_POINT) {
-    const long long idx = ((long long)adj->r0[2] * p->ny + adj->r0[1]) * p->nx + adj->r0[0];
-    hipLaunchKernelGGL(k_point_amp, dim3(1), dim3(64), 0, p->stream, p->state,
-                       static_cast<const float2*>(E_fwd), idx, a.sE, E_fwd ? 1 : 0,
-                       (float)(p->pitch * p->pitch),
-                       make_float2((float)adj->amp[0][0], (float)adj->amp[0][1]),
-                       make_float2((float)adj->amp[1][0], (float)adj->amp[1][1]),
-                       make_float2((float)adj->amp[2][0], (float)adj->amp[2][1]));
-    HIP_LAUNCHED();
+  return advance_solve(p, iters);
+}
+
+int cbs_solve_poll(cbs_plan_t p, int* done, int* outstanding) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  rc = poll_solve(p, done);
+  if (outstanding) *outstanding = p->act.count;
+  return rc;
+}
+
+int cbs_solve_end(cbs_plan_t p, cbs_stats* stats) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  return end_solve(p, stats);
+}
+
+int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out) {
+  if (count < 0 || (count > 0 && (!plans || !done_out)))
+    return fail(CBS_E_INVALID, "bad plan array");
+  for (int i = 0; i < count; ++i) {
+    int rc = check_plan(plans[i], true);
+    if (rc) return rc;
+    if (!plans[i]->act.on) return fail(CBS_E_STATE, "plan %d has no solve in progress", i);
   }
-  return iterate(p, a, o, stats);
+  // enqueue every plan's quantum first (each on its own stream), then wait
+  for (int i = 0; i < count; ++i) {
+    int rc = advance_solve(plans[i], iters);
+    if (rc) return rc;
+  }
+  for (int i = 0; i < count; ++i) {
+    int rc = wait_solve(plans[i]);
+    if (rc) return rc;
+    done_out[i] = plans[i]->act.stopped ? 1 : 0;
+  }
+  return CBS_OK;
 }
 
 int cbs_gradient(cbs_plan_t p, const void* E, const void* Ea, const int lo[3], const int hi[3],
@@ -873,9 +1015,13 @@ int cbs_history(cbs_plan_t p, double* out, int max) {
 
 int cbs_plan_destroy(cbs_plan_t p) {
   if (!p) return CBS_OK;
+  // outstanding asynchronous copies target the pinned mirror: drain first
+  if (p->act.on || p->act.count > 0) (void)hipStreamSynchronize(p->stream);
   (void)hipEventDestroy(p->ev0);
   (void)hipEventDestroy(p->ev1);
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(p->evp[i]);
+  for (int i = 0; i < cbs_plan_s::kRing; ++i) (void)hipEventDestroy(p->evq[i]);
+  (void)hipHostFree(p->mirror);
   delete p;
   return CBS_OK;
 }

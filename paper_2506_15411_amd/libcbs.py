@@ -64,6 +64,7 @@ _lib = None
 SYMBOLS = [
     "cbs_plan_workspace_bytes", "cbs_axis_supported", "cbs_plan_create",
     "cbs_plan_set_pml_profile", "cbs_plan_set_shift_factor", "cbs_set_permittivity", "cbs_solve", "cbs_adjoint_solve",
+    "cbs_solve_begin", "cbs_solve_advance", "cbs_solve_poll", "cbs_solve_end", "cbs_batch_step",
     "cbs_gradient", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
     "cbs_last_error",
 ]
@@ -98,6 +99,16 @@ def load(path: str | None = None):
     lib.cbs_adjoint_solve.argtypes = [c_void_p, c_void_p, P(cbs_source), c_void_p, P(cbs_opts),
                                       P(cbs_stats)]
     lib.cbs_adjoint_solve.restype = c_int
+    lib.cbs_solve_begin.argtypes = [c_void_p, c_int, c_void_p, P(cbs_source), c_void_p, P(cbs_opts)]
+    lib.cbs_solve_begin.restype = c_int
+    lib.cbs_solve_advance.argtypes = [c_void_p, c_int]
+    lib.cbs_solve_advance.restype = c_int
+    lib.cbs_solve_poll.argtypes = [c_void_p, P(c_int), P(c_int)]
+    lib.cbs_solve_poll.restype = c_int
+    lib.cbs_solve_end.argtypes = [c_void_p, P(cbs_stats)]
+    lib.cbs_solve_end.restype = c_int
+    lib.cbs_batch_step.argtypes = [P(c_void_p), c_int, c_int, P(c_int)]
+    lib.cbs_batch_step.restype = c_int
     lib.cbs_gradient.argtypes = [c_void_p, c_void_p, c_void_p, P(c_int), P(c_int), c_double,
                                  c_void_p]
     lib.cbs_gradient.restype = c_int
@@ -178,6 +189,38 @@ def cbs_adjoint_solve(plan, E_fwd_ptr, src: cbs_source, E_adj_ptr, opts: cbs_opt
                                   ctypes.byref(st))
     check(rc, allow_not_converged=True)
     return rc, st
+
+
+def cbs_solve_begin(plan, adjoint: int, E_fwd_ptr, src: cbs_source | None, E_ptr, opts: cbs_opts):
+    return check(load().cbs_solve_begin(plan, int(adjoint), ctypes.c_void_p(E_fwd_ptr),
+                                        ctypes.byref(src) if src is not None else None,
+                                        ctypes.c_void_p(E_ptr), ctypes.byref(opts)))
+
+
+def cbs_solve_advance(plan, iters):
+    return check(load().cbs_solve_advance(plan, int(iters)))
+
+
+def cbs_solve_poll(plan):
+    """(done, outstanding quanta)"""
+    done = ctypes.c_int(0)
+    out = ctypes.c_int(0)
+    check(load().cbs_solve_poll(plan, ctypes.byref(done), ctypes.byref(out)))
+    return bool(done.value), int(out.value)
+
+
+def cbs_solve_end(plan):
+    st = cbs_stats()
+    rc = load().cbs_solve_end(plan, ctypes.byref(st))
+    check(rc, allow_not_converged=True)
+    return rc, st
+
+
+def cbs_batch_step(plans, iters):
+    arr = (ctypes.c_void_p * len(plans))(*[p.value if isinstance(p, ctypes.c_void_p) else p for p in plans])
+    done = (ctypes.c_int * max(1, len(plans)))()
+    check(load().cbs_batch_step(arr, len(plans), int(iters), done))
+    return [bool(done[i]) for i in range(len(plans))]
 
 
 def cbs_gradient(plan, E_ptr, E_adj_ptr, box_lo, box_hi, scale, grad_ptr):

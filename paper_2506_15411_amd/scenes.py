@@ -271,3 +271,72 @@ def random_field(shape, seed: int, scale: float = 1.0) -> np.ndarray:
     rng = np.random.default_rng(seed)
     f = rng.standard_normal((2, 3, nz, ny, nx)) * scale
     return (f[0] + 1j * f[1]).astype(np.complex64)
+
+
+# ---------------------------------------------------------------------------
+# Served batch: a seeded stream of mixed-size forward / adjoint requests
+# ---------------------------------------------------------------------------
+SERVED_GRIDS = (
+    ((64, 64, 64), LAMBDA0 / 6),
+    ((128, 128, 128), LAMBDA0 / 6),
+    ((192, 192, 256), LAMBDA0 / 12),
+    ((275, 275, 315), LAMBDA0 / 16),
+)
+
+
+@dataclasses.dataclass
+class ServedRequest:
+    """One request of a served trace: a scene, its kind and its arrival time."""
+
+    rid: int
+    kind: str            # "forward" or "adjoint" (forward + adjoint + gradient)
+    scene: Scene
+    arrival: float       # seconds after the start of the trace
+
+
+def served_scene(rng: np.random.Generator, grid=None, name="served") -> Scene:
+    """Random sphere or zone plate, n ~ U[1.3, 1.6], on one of the served grids."""
+    if grid is None:
+        grid = SERVED_GRIDS[int(rng.integers(len(SERVED_GRIDS)))]
+    shape, pitch = grid
+    nx, ny, nz = shape
+    pml = pml_voxels(pitch)
+    n_obj = float(rng.uniform(1.3, 1.6))
+    ix, iy, iz = nx - 2 * pml[0], ny - 2 * pml[1], nz - 2 * pml[2]
+    if rng.random() < 0.5:
+        rmax = 0.35 * min(ix, iy, iz) * pitch
+        radius = float(rng.uniform(0.5e-6, max(0.5e-6, rmax)))
+        jit = rng.uniform(-1.0, 1.0, size=3) * pitch
+        c = ((nx - 1) / 2 * pitch + jit[0], (ny - 1) / 2 * pitch + jit[1], (nz - 1) / 2 * pitch + jit[2])
+        f = sphere_fraction(shape, pitch, radius, center=c, supersample=4)
+        eps = (1.0 + f * (n_obj ** 2 - 1.0)).astype(np.float32)
+        _clear_layer(eps, pml, 1.0)
+        zf = int(round((c[2] + radius + 1e-6) / pitch))
+        r0 = ((nx - 1) // 2, (ny - 1) // 2, min(zf, nz - pml[2] - 1))
+        sc = Scene(name=name, shape=shape, pitch=pitch, pml=pml, eps_r=eps, r0=r0,
+                   info=dict(kind="sphere", radius=radius, n=n_obj))
+        lo = (pml[0], pml[1], pml[2])
+        hi = (nx - pml[0], ny - pml[1], nz - pml[2])
+    else:
+        D = min(16e-6, 0.9 * min(ix, iy) * pitch)
+        sc = zone_plate_scene(shape, pitch, D, 0.84, n_obj, pml=pml, supersample=4, name=name)
+        zb = sc.info["z_base"]
+        lo = (pml[0], pml[1], zb)
+        hi = (nx - pml[0], ny - pml[1], zb + max(1, int(round(2e-6 / pitch))))
+        sc.info["kind"] = "zoneplate"
+    return dataclasses.replace(sc, design_box=(lo, hi))
+
+
+def served_trace(n_requests: int = 200, rate_hz: float = 5.0, seed: int = 0, grids=None):
+    """Poisson arrivals (numpy default_rng(seed)) of forward/adjoint requests
+    at 50/50, grids uniform over `grids` (default: the four served grids)."""
+    rng = np.random.default_rng(seed)
+    grids = SERVED_GRIDS if grids is None else grids
+    t = 0.0
+    out = []
+    for i in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_hz))
+        grid = grids[int(rng.integers(len(grids)))]
+        kind = "forward" if rng.random() < 0.5 else "adjoint"
+        out.append(ServedRequest(i, kind, served_scene(rng, grid, name=f"req{i}"), t))
+    return out

@@ -99,13 +99,7 @@ class Plan:
             | (L.CBS_RECORD_HISTORY if history else 0)
         return L.cbs_opts(float(tol), int(max_iter), int(check_every), flags)
 
-    def solve(self, E: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
-              warm=False, scattered=False, history=False, pol=None, field=None, point=None,
-              kind=None):
-        """Forward solve (plane wave by default).  Returns (E, SolveStats)."""
-        if E is None:
-            E = self.new_field()
-        _require_gpu(E, "E", torch.complex64, self.fshape)
+    def _forward_source(self, pol=None, field=None, point=None, kind=None):
         src = L.cbs_source()
         if field is not None:
             _require_gpu(field, "field", torch.complex64, self.fshape)
@@ -124,19 +118,9 @@ class Plan:
                 for c in range(3):
                     a = complex(pol[c])
                     src.pol[c][0], src.pol[c][1] = a.real, a.imag
-        rc, st = L.cbs_solve(self.handle, src, E.data_ptr(),
-                             self._opts(tol, max_iter, check_every, warm, scattered, history))
-        return E, _stats(rc, st)
+        return src
 
-    def adjoint(self, E_fwd: torch.Tensor | None = None, r0=None, amp=None, field=None,
-                E_adj: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
-                warm=False, history=False):
-        """Adjoint solve.  With r0 and E_fwd: source conj(E_fwd(r0)) at r0
-        (objective |E(r0)|^2).  With r0 and amp: that amplitude.  With field:
-        a general source.  Returns (E_adj, SolveStats)."""
-        if E_adj is None:
-            E_adj = self.new_field()
-        _require_gpu(E_adj, "E_adj", torch.complex64, self.fshape)
+    def _adjoint_source(self, E_fwd=None, r0=None, amp=None, field=None):
         src = L.cbs_source()
         fptr = 0
         if field is not None:
@@ -154,9 +138,60 @@ class Plan:
             else:
                 _require_gpu(E_fwd, "E_fwd", torch.complex64, self.fshape)
                 fptr = E_fwd.data_ptr()
+        return src, fptr
+
+    def solve(self, E: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
+              warm=False, scattered=False, history=False, pol=None, field=None, point=None,
+              kind=None):
+        """Forward solve (plane wave by default).  Returns (E, SolveStats)."""
+        if E is None:
+            E = self.new_field()
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        src = self._forward_source(pol, field, point, kind)
+        self._src_keep = src
+        rc, st = L.cbs_solve(self.handle, src, E.data_ptr(),
+                             self._opts(tol, max_iter, check_every, warm, scattered, history))
+        return E, _stats(rc, st)
+
+    def adjoint(self, E_fwd: torch.Tensor | None = None, r0=None, amp=None, field=None,
+                E_adj: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
+                warm=False, history=False):
+        """Adjoint solve.  With r0 and E_fwd: source conj(E_fwd(r0)) at r0
+        (objective |E(r0)|^2).  With r0 and amp: that amplitude.  With field:
+        a general source.  Returns (E_adj, SolveStats)."""
+        if E_adj is None:
+            E_adj = self.new_field()
+        _require_gpu(E_adj, "E_adj", torch.complex64, self.fshape)
+        src, fptr = self._adjoint_source(E_fwd, r0, amp, field)
         rc, st = L.cbs_adjoint_solve(self.handle, fptr, src, E_adj.data_ptr(),
                                      self._opts(tol, max_iter, check_every, warm, False, history))
         return E_adj, _stats(rc, st)
+
+    # -- asynchronous solves (one at a time per plan; plans overlap) ---------
+    def begin(self, E: torch.Tensor, adjoint=False, E_fwd=None, r0=None, amp=None, field=None,
+              tol=1e-4, max_iter=20000, warm=False, scattered=False, history=False, pol=None):
+        """Start a solve into E without waiting (see cbs_solve_begin)."""
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        if adjoint:
+            src, fptr = self._adjoint_source(E_fwd, r0, amp, field)
+        else:
+            src, fptr = self._forward_source(pol, field, None, None), 0
+        opts = self._opts(tol, max_iter, 1, warm, scattered, history)
+        L.cbs_solve_begin(self.handle, 1 if adjoint else 0, fptr, src, E.data_ptr(), opts)
+        self._async_keep = (E, E_fwd, field)
+        return E
+
+    def advance(self, iters: int):
+        L.cbs_solve_advance(self.handle, iters)
+
+    def poll(self):
+        """(done, outstanding quanta) without waiting."""
+        return L.cbs_solve_poll(self.handle)
+
+    def end(self) -> SolveStats:
+        rc, st = L.cbs_solve_end(self.handle)
+        self._async_keep = None
+        return _stats(rc, st)
 
     def gradient(self, E: torch.Tensor, E_adj: torch.Tensor, box_lo=None, box_hi=None,
                  scale=2.0, out: torch.Tensor | None = None):
