@@ -210,7 +210,9 @@ int cbs_history(cbs_plan_t plan, double* out_host, int max);
  * iterations (no early stop) into E_dev, with HIP events recorded on the
  * plan's stream between the passes, and return the mean device time per
  * launch in ms_out[0..4] = { y forward, z (forward + Green + inverse),
- * y inverse, x (inverse + update + forward), residual }.  Synchronises. */
+ * y inverse, x (inverse + update + forward), residual } (the residual
+ * reduction normally runs inside the x pass; ms_out[4] is then 0).
+ * Synchronises. */
 int cbs_time_passes(cbs_plan_t plan, void* E_dev, int iters, float* ms_out);
 
 /* Measurement aid (no plan needed): copy `bytes` (a multiple of 16) from

@@ -96,3 +96,41 @@ def slab_1d(nz: int, pitch: float, lambda0: float, n_bg: float, pml_z: int,
     D2 = (F.conj().T / nz) @ ((pz ** 2)[:, None] * F)
     A = D2 - np.diag(K)
     return np.linalg.solve(A, np.asarray(s_z, dtype=np.complex128))
+
+
+def uniform_medium_modes(g, eps_const: complex, modes, iterations: int):
+    """Closed form for a source made of single Fourier modes in a uniform medium.
+
+    modes: list of ((kx, ky, kz) FFT indices, s (3 complex)) with the source
+    S(r) = sum_m s_m exp(i p_m . r).  Each mode stays a single mode:
+    E_k(r) = sum_m exp(i p_m . r) e_m^(k), where e^(k) follows the 3x3 affine
+    map e <- (1 - gamma) e + gamma inv(M(p) - kt2 I) (V e + s), e^(0) = 0, with
+    the matrix inverted explicitly.  Returns [(p_m (x, y, z), e_m^(k))] with p
+    in rad/m; evaluating at any voxel costs O(#modes), so this checks the
+    iteration at any grid size."""
+    k0sq = g.k0 ** 2
+    kb2 = g.kb ** 2
+    V0 = k0sq * (complex(eps_const) - g.n_bg ** 2)
+    eps = g.shift_factor * max(abs(V0), 1e-3 * kb2)
+    V = V0 - 1j * eps
+    gamma = 1j * V / eps
+    kt2 = kb2 + 1j * eps
+    out = []
+    for (kx, ky, kz), s in modes:
+        p = []
+        pt = []
+        for k, n in ((kx, g.nx), (ky, g.ny), (kz, g.nz)):
+            m = k if k < (n + 1) // 2 else k - n
+            pa = 2.0 * math.pi * m / (n * g.pitch)
+            p.append(pa)
+            pt.append(0.0 if (n % 2 == 0 and 2 * k == n) else pa)
+        p = np.array(p)
+        pt = np.array(pt)
+        M = np.dot(p, p) * np.eye(3) - np.outer(pt, pt)
+        G = np.linalg.inv(M - kt2 * np.eye(3))
+        s = np.asarray(s, dtype=np.complex128)
+        e = np.zeros(3, dtype=np.complex128)
+        for _ in range(iterations):
+            e = (1 - gamma) * e + gamma * (G @ (V * e + s))
+        out.append((p, e))
+    return out

@@ -157,6 +157,7 @@ __global__ void k_state_init(DevState* st, double tol, int max_iter, int record)
     st->tol = tol;
     st->eta = INFINITY;
     st->record = record;
+    st->arrive = 0u;
   }
 }
 
@@ -177,49 +178,14 @@ __global__ void k_point_amp(DevState* st, const float2* E, long long idx, long l
   }
 }
 
-// eta = sqrt(sum |dE|^2 / sum |E|^2) over the K1 block partials (fixed order)
+// eta = sqrt(sum |dE|^2 / sum |E|^2) over the K1 block partials (fixed order);
+// a separate launch when the x-pass does not fold it in
 constexpr int kResThreads = 256;
 __global__ void __launch_bounds__(kResThreads)
 k_residual(const double* part, int nb, DevState* st, double* hist) {
   __shared__ double s0[kResThreads], s1[kResThreads];
   if (st->done) return;
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kResThreads) {
-    a += part[2 * i];
-    b += part[2 * i + 1];
-  }
-  s0[threadIdx.x] = a;
-  s1[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = kResThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s0[threadIdx.x] += s0[threadIdx.x + w];
-      s1[threadIdx.x] += s1[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double nd = s0[0], ne = s1[0];
-    double eta;
-    if (ne > 0.0)
-      eta = sqrt(nd / ne);
-    else
-      eta = (nd == 0.0) ? 0.0 : INFINITY;
-    const int it = st->iter + 1;
-    st->iter = it;
-    st->eta = eta;
-    if (st->record && it <= kHistCap) hist[it - 1] = eta;
-    if (!isfinite(eta)) {
-      st->status = 3;
-      st->done = 1;
-    } else if (eta <= st->tol) {
-      st->status = 1;
-      st->done = 1;
-    } else if (it >= st->max_iter) {
-      st->status = 2;
-      st->done = 1;
-    }
-  }
+  residual_finish<kResThreads>(part, nb, st, hist, s0, s1);
 }
 
 // E += sign * pol exp(i kb z)  (incident field)
@@ -355,12 +321,18 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   return true;
 }
 
-void fill_twiddles(std::vector<float2>& t, int n) {
+// Twiddles of a two-level split n = n1 n2: t[j2 n1 + k1] = exp(-2 pi i j2 k1 / n),
+// j2 < n2, k1 < n1 (FP64 on the host, rounded to FP32).  j2 k1 < n, so the
+// angle needs no reduction, and the same table read at [k][t] serves the
+// transposed split.
+void fill_twiddles(std::vector<float2>& t, int n1, int n2) {
+  const int n = n1 * n2;
   t.resize(n);
-  for (int m = 0; m < n; ++m) {
-    const double ang = -2.0 * M_PI * double(m) / double(n);
-    t[m] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
+  for (int j2 = 0; j2 < n2; ++j2)
+    for (int k1 = 0; k1 < n1; ++k1) {
+      const double ang = -2.0 * M_PI * double(j2 * k1) / double(n);
+      t[j2 * n1 + k1] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
 }
 
 CbsArgs base_args(cbs_plan_s* p) {
@@ -419,8 +391,9 @@ int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
   p->oz->kz(a, p->stream);
   p->oy->ky(a, +1, p->stream);
   p->ox->k1(a, K1_ITER, p->stream);
-  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
-                     p->k1_blocks, p->state, p->hist);
+  if (!CBS_FOLD_RESIDUAL)
+    hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
+                       p->k1_blocks, p->state, p->hist);
   HIP_LAUNCHED();
   return CBS_OK;
 }
@@ -718,9 +691,9 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
   p->hist_len = 0;
 
   std::vector<float2> tx, ty, tz, ph(nz);
-  fill_twiddles(tx, nx);
-  fill_twiddles(ty, ny);
-  fill_twiddles(tz, nz);
+  fill_twiddles(tx, p->ox->n1, p->ox->n2);
+  fill_twiddles(ty, p->oy->n1, p->oy->n2);
+  fill_twiddles(tz, p->oz->z1, p->oz->z2);
   for (int k = 0; k < nz; ++k) {
     const double ang = p->kb * pitch_m * k;
     ph[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
@@ -959,8 +932,9 @@ int cbs_time_passes(cbs_plan_t p, void* E_dev, int iters, float* ms_out) {
     HIP_TRY(hipEventRecord(p->evp[3], p->stream));
     p->ox->k1(a, K1_ITER, p->stream);
     HIP_TRY(hipEventRecord(p->evp[4], p->stream));
-    hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
-                       p->k1_blocks, p->state, p->hist);
+    if (!CBS_FOLD_RESIDUAL)
+      hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
+                         p->k1_blocks, p->state, p->hist);
     HIP_LAUNCHED();
     HIP_TRY(hipEventRecord(p->evp[5], p->stream));
     HIP_TRY(hipEventSynchronize(p->evp[5]));

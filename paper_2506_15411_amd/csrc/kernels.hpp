@@ -44,6 +44,28 @@ enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
 
 constexpr int kHistCap = 1 << 16;
 
+// Tuning knobs (compile-time; the defaults are the measured best on gfx950)
+#ifndef CBS_K1_THREADS
+#define CBS_K1_THREADS 256   // target threads per x-pass block (rows per block follow)
+#endif
+#ifndef CBS_K1_PREFETCH
+#define CBS_K1_PREFETCH 2    // x-pass: 1 = load V0, 2 = load V0 and E_s before the inverse FFT
+#endif
+#ifndef CBS_TY
+#define CBS_TY 8             // columns per y-pass block
+#endif
+#ifndef CBS_TZ
+#define CBS_TZ 8             // columns per z-pass block
+#endif
+#ifndef CBS_Y_TW_GLOBAL
+#define CBS_Y_TW_GLOBAL 0    // y pass: read twiddles from global memory (frees LDS for a 4th block)
+#endif
+#ifndef CBS_FOLD_RESIDUAL
+#define CBS_FOLD_RESIDUAL 0  // 1: last x-pass block reduces the residual; its device-scope
+                             // fences write back the per-XCD L2s, which costs more than the
+                             // separate reduction launch on this part
+#endif
+
 // Device-resident solve state (lives in the workspace).
 struct DevState {
   int done;        // 1: stop iterating (kernels return at entry)
@@ -54,8 +76,52 @@ struct DevState {
   double eta;      // last relative update norm
   float2 amp[3];   // point-source amplitude (already scaled by d^2)
   int record;      // keep eta history
-  int pad;
+  unsigned arrive; // x-pass blocks that have written their residual partials
 };
+
+// Fixed-order sum of the per-block partials, then the stopping rule.  Run by
+// one block (THREADS threads); deterministic whatever block runs it.
+template <int THREADS>
+__device__ __forceinline__ void residual_finish(const double* part, int nb, DevState* st,
+                                                double* hist, double* s0, double* s1) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += THREADS) {
+    a += __builtin_nontemporal_load(part + 2 * i);
+    b += __builtin_nontemporal_load(part + 2 * i + 1);
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      s0[threadIdx.x] += s0[threadIdx.x + w];
+      s1[threadIdx.x] += s1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nd = s0[0], ne = s1[0];
+    double eta;
+    if (ne > 0.0)
+      eta = sqrt(nd / ne);
+    else
+      eta = (nd == 0.0) ? 0.0 : INFINITY;
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->eta = eta;
+    if (st->record && it <= kHistCap) hist[it - 1] = eta;
+    if (!isfinite(eta)) {
+      st->status = 3;
+      st->done = 1;
+    } else if (eta <= st->tol) {
+      st->status = 1;
+      st->done = 1;
+    } else if (it >= st->max_iter) {
+      st->status = 2;
+      st->done = 1;
+    }
+  }
+}
 
 struct CbsArgs {
   int nx, ny, nz, nxp;          // grid, padded row pitch of W
@@ -65,9 +131,9 @@ struct CbsArgs {
   float2* W;                    // spectral work field [3][nz][ny][nxp]
   float2* E;                    // E_s, caller layout [3][nz][ny][nx]
   const float2* V0;             // unshifted potential * d^2, [nz][ny][nx]
-  const float2* twx;            // exp(-2 pi i m / nx), m < nx
-  const float2* twy;
-  const float2* twz;
+  const float2* twx;            // x split n1 x n2: twx[j2 n1 + k1] = exp(-2 pi i j2 k1 / nx)
+  const float2* twy;            // same layout for the y split
+  const float2* twz;            // same layout for the z split
   const float2* phase;          // exp(i kb d k), k < nz
   const float2* fin;            // FIELD source / Green input
   float2* fout;                 // Green output
@@ -95,7 +161,7 @@ template <int N1, int N2>
 struct XGeom {
   static constexpr int N = N1 * N2;
   static constexpr int TM = cmax(N1, N2);
-  static constexpr int LINES = cmax(1, 256 / (3 * TM));
+  static constexpr int LINES = cmax(1, CBS_K1_THREADS / (3 * TM));
   static constexpr int THREADS = round64(3 * LINES * TM);
 };
 template <int N1, int N2, int TX>
@@ -125,9 +191,9 @@ __device__ __forceinline__ float freq_of(int k, int n, float pf, bool& nyq) {
 // that each XCD walks a contiguous range of tiles puts both halves of a line
 // in the same L2 at about the same time.  Bijective for any block count.
 constexpr int kXcds = 8;
-__device__ __forceinline__ long long xcd_remap(long long b, long long total) {
-  const long long q = total / kXcds, r = total % kXcds;
-  const long long k = b % kXcds, j = b / kXcds;
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned total) {
+  const unsigned q = total / kXcds, r = total % kXcds;
+  const unsigned k = b % kXcds, j = b / kXcds;
   return k * q + (k < r ? k : r) + j;
 }
 
@@ -193,18 +259,28 @@ k1_xpass(CbsArgs a) {
   __syncthreads();
 
   float2 v[N2];  // thread t (< N1): element t + N1 m, m < N2
+  // optional early loads of the pointwise operands (their latency then hides
+  // behind the inverse transform)
+  constexpr bool PF_V = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 1;
+  constexpr bool PF_E = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 2;
+  float2 pv[PF_V ? N2 : 1], pe[PF_E ? N2 : 1];
+  const float2* v0t = a.V0 + vbase + t;   // this thread's elements are t + N1 m
+  float2* et = a.E + ebase + t;
+  if constexpr (PF_V) {
+    if (ok && t < N1) sfor<0, N2>([&](auto M) { pv[CV(M)] = v0t[N1 * CV(M)]; });
+  }
+  if constexpr (PF_E) {
+    if (ok && t < N1) sfor<0, N2>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
+  }
   if constexpr (MODE != K1_FWD) {
     // inverse level A: thread j2 = t < N2, DFT-N1 over Wrow[j2 + N2 j1]
     if (ok && t < N2) {
       float2 b[N1];
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = Wrow[t + N2 * CV(J1)]; });
+      const float2* wt = Wrow + t;
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = wt[N2 * CV(J1)]; });
       dft<N1, +1>(b);
-      int idx = 0;
-      sfor<0, N1>([&](auto K1) {
-        b[CV(K1)] = cmulc(b[CV(K1)], tw[idx]);
-        idx += t;
-        if (idx >= N) idx -= N;
-      });
+      const float2* twt = tw + t * N1;   // exp(-2 pi i t k1 / N), conjugated below
+      sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmulc(b[CV(K1)], twt[CV(K1)]); });
       sfor<0, N1>([&](auto K1) { L[t + N2 * CV(K1)] = b[CV(K1)]; });
     }
     __syncthreads();
@@ -233,22 +309,23 @@ k1_xpass(CbsArgs a) {
     sfor<0, N2>([&](auto M) {
       const int x = t + N1 * CV(M);
       float2 e;
-      const float2 v0 = a.V0[vbase + x];
+      float2 v0;
+      if constexpr (PF_V) v0 = pv[CV(M)]; else v0 = v0t[N1 * CV(M)];
       if constexpr (MODE == K1_ITER) {
-        e = a.E[ebase + x];
+        if constexpr (PF_E) e = pe[CV(M)]; else e = et[N1 * CV(M)];
         // gamma = 1 + i V0 / eps
         const float2 gm = make_float2(1.0f - v0.y * a.inv_eps, v0.x * a.inv_eps);
         const float2 d = cmul(gm, csub(v[CV(M)], e));
         e = cadd(e, d);
         sd += (double)(d.x * d.x + d.y * d.y);
         se += (double)(e.x * e.x + e.y * e.y);
-        a.E[ebase + x] = e;
+        et[N1 * CV(M)] = e;
       } else if (a.warm) {
-        e = a.E[ebase + x];
+        e = et[N1 * CV(M)];
       } else {
         // cold start: E_s^(0) = 0, whatever the output buffer held
         e = make_float2(0.f, 0.f);
-        if (!a.green_in) a.E[ebase + x] = e;
+        if (!a.green_in) et[N1 * CV(M)] = e;
       }
       float2 w;
       if (MODE == K1_FWD && a.green_in) {
@@ -269,12 +346,8 @@ k1_xpass(CbsArgs a) {
     });
     // forward level A' (split N2 x N1): DFT-N2 over v, twiddle, to L[t + N1 k1']
     dft<N2, -1>(v);
-    int idx = 0;
-    sfor<0, N2>([&](auto K) {
-      L[t + N1 * CV(K)] = cmul(v[CV(K)], tw[idx]);
-      idx += t;
-      if (idx >= N) idx -= N;
-    });
+    const float2* twc = tw + t;   // exp(-2 pi i t k / N) sits at [k][t] of the table
+    sfor<0, N2>([&](auto K) { L[t + N1 * CV(K)] = cmul(v[CV(K)], twc[N1 * CV(K)]); });
   }
   __syncthreads();
   // forward level B': thread k1' = t < N2, DFT-N1 over L[N1 k1' + j2']
@@ -282,10 +355,36 @@ k1_xpass(CbsArgs a) {
     float2 b[N1];
     sfor<0, N1>([&](auto J) { b[CV(J)] = L[N1 * t + CV(J)]; });
     dft<N1, -1>(b);
-    sfor<0, N1>([&](auto K) { Wrow[t + N2 * CV(K)] = b[CV(K)]; });
+    float2* wt = Wrow + t;
+    sfor<0, N1>([&](auto K) { wt[N2 * CV(K)] = b[CV(K)]; });
   }
   if constexpr (MODE == K1_ITER) {
     block_sum2<G::THREADS>(sd, se, red, a.partials + 2 * (long long)blockIdx.x);
+#if CBS_FOLD_RESIDUAL
+    // the last block to arrive finishes the reduction: release this block's
+    // partials device-wide, count arrivals, acquire before reading the rest
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned prev = atomicAdd(&a.st->arrive, 1u);
+      last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last) {
+      __threadfence();
+      // all reads of lds ended before block_sum2's barrier: reuse it as scratch
+      constexpr bool kFits = sizeof(lds) >= 2 * G::THREADS * sizeof(double);
+      if constexpr (kFits) {
+        double* s0 = reinterpret_cast<double*>(lds);
+        residual_finish<G::THREADS>(a.partials, (int)gridDim.x, a.st, a.hist, s0,
+                                    s0 + G::THREADS);
+      } else {
+        __shared__ double s0[G::THREADS], s1[G::THREADS];
+        residual_finish<G::THREADS>(a.partials, (int)gridDim.x, a.st, a.hist, s0, s1);
+      }
+      if (threadIdx.x == 0) a.st->arrive = 0u;
+    }
+#endif
   }
 }
 
@@ -298,17 +397,23 @@ ky_pass(CbsArgs a) {
   using G = YGeom<N1, N2, TX>;
   constexpr int N = G::N;
   __shared__ float2 lds[N * TX];
+#if CBS_Y_TW_GLOBAL
+  const float2* tw = a.twy;
+#else
   __shared__ float2 tw[N];
+#endif
   if (a.st->done) return;
   const int tid = threadIdx.x;
+#if !CBS_Y_TW_GLOBAL
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
+#endif
   const int xi = tid % TX;
   const int t = tid / TX;
-  const int gx = (a.nx + TX - 1) / TX;
-  const long long L = xcd_remap(blockIdx.x, (long long)gx * a.nz * 3);
+  const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
+  const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.nz * 3u);
   const int bx = (int)(L % gx);
-  const long long rest = L / gx;
-  const int z = (int)(rest % a.nz), c = (int)(rest / a.nz);
+  const unsigned rest = L / gx;
+  const int z = (int)(rest % (unsigned)a.nz), c = (int)(rest / (unsigned)a.nz);
   const int x = bx * TX + xi;
   const bool xok = x < a.nx;
   float2* col = a.W + c * a.sW + (long long)z * a.ny * a.nxp + (xok ? x : 0);
@@ -317,17 +422,18 @@ ky_pass(CbsArgs a) {
   if (t < N2) {
     float2 b[N1];
     if (xok) {
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[(t + N2 * CV(J1)) * ps]; });
+      // per-thread base once; each load then adds a uniform stride
+      const float2* ct = col + (long long)t * ps;
+      const long long st = (long long)N2 * ps;
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = ct[CV(J1) * st]; });
     } else {
       sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
     }
     dft<N1, S>(b);
-    int idx = 0;
+    const float2* twt = tw + t * N1;
     sfor<0, N1>([&](auto K1) {
-      const float2 w = tw[idx];
+      const float2 w = twt[CV(K1)];
       b[CV(K1)] = (S < 0) ? cmul(b[CV(K1)], w) : cmulc(b[CV(K1)], w);
-      idx += t;
-      if (idx >= N) idx -= N;
     });
     sfor<0, N1>([&](auto K1) { lds[(t + N2 * CV(K1)) * TX + xi] = b[CV(K1)]; });
   }
@@ -336,7 +442,9 @@ ky_pass(CbsArgs a) {
     float2 v[N2];
     sfor<0, N2>([&](auto J2) { v[CV(J2)] = lds[(N2 * t + CV(J2)) * TX + xi]; });
     dft<N2, S>(v);
-    sfor<0, N2>([&](auto K2) { col[(t + N1 * CV(K2)) * ps] = v[CV(K2)]; });
+    float2* ct = col + (long long)t * ps;
+    const long long st = (long long)N1 * ps;
+    sfor<0, N2>([&](auto K2) { ct[CV(K2) * st] = v[CV(K2)]; });
   }
 }
 
@@ -355,8 +463,8 @@ kz_pass(CbsArgs a) {
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
   const int xi = tid % TX;
   const int t = tid / TX;
-  const int gx = (a.nx + TX - 1) / TX;
-  const long long L = xcd_remap(blockIdx.x, (long long)gx * a.ny);
+  const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
+  const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.ny);
   const int bx = (int)(L % gx);
   const int y = (int)(L / gx);
   const int x = bx * TX + xi;
@@ -368,21 +476,18 @@ kz_pass(CbsArgs a) {
   // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
   const int ca = t / N2;
   const int j2 = t - ca * N2;
+  const long long zst = (long long)N2 * plane;  // uniform stride between a thread's z samples
   if (t < 3 * N2) {
-    float2* col = colbase + ca * a.sW;
+    const float2* col = colbase + ca * a.sW + (long long)j2 * plane;
     float2 b[N1];
     if (xok) {
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[(j2 + N2 * CV(J1)) * plane]; });
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[CV(J1) * zst]; });
     } else {
       sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
     }
     dft<N1, -1>(b);
-    int idx = 0;
-    sfor<0, N1>([&](auto K1) {
-      b[CV(K1)] = cmul(b[CV(K1)], tw[idx]);
-      idx += j2;
-      if (idx >= N) idx -= N;
-    });
+    const float2* twt = tw + j2 * N1;
+    sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmul(b[CV(K1)], twt[CV(K1)]); });
     float2* Lc = lds + ca * N * TX;
     sfor<0, N1>([&](auto K1) { Lc[(j2 + N2 * CV(K1)) * TX + xi] = b[CV(K1)]; });
   }
@@ -410,6 +515,9 @@ kz_pass(CbsArgs a) {
     const float pxy2 = px * px + py * py;
     const float nq_xy = (nyx ? px * px : 0.f) + (nyy ? py * py : 0.f);
     const float eps = a.eps, e2 = eps * eps;
+    const bool nq_any = nyx || nyy;
+    const float sb = __builtin_amdgcn_rcpf(a.kb2 * a.kb2 + e2);
+    const float2 gb0 = make_float2(-a.kb2 * sb, eps * sb);
     sfor<0, N2>([&](auto K2) {
       constexpr int k2 = CV(K2);
       bool nyz;
@@ -420,9 +528,12 @@ kz_pass(CbsArgs a) {
       const float r1 = p2 - a.kb2;
       const float s1 = a.invN * __builtin_amdgcn_rcpf(r1 * r1 + e2);
       const float2 ga = make_float2(r1 * s1, eps * s1);
-      const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
-      const float s2 = __builtin_amdgcn_rcpf(r2 * r2 + e2);
-      const float2 gb = make_float2(r2 * s2, eps * s2);
+      float2 gb = gb0;   // 1 / (-kb2 - i eps): every mode without a Nyquist component
+      if (nq_any || nyz) {
+        const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
+        const float s2 = __builtin_amdgcn_rcpf(r2 * r2 + e2);
+        gb = make_float2(r2 * s2, eps * s2);
+      }
       const float2 u0 = v0[k2], u1 = v1[k2], u2 = v2[k2];
       const float2 sp = make_float2(ptx * u0.x + pty * u1.x + ptz * u2.x,
                                     ptx * u0.y + pty * u1.y + ptz * u2.y);
@@ -448,15 +559,11 @@ kz_pass(CbsArgs a) {
     float2* Lc = lds + ca * N * TX;
     float2 b[N1];
     sfor<0, N1>([&](auto K1) { b[CV(K1)] = Lc[(j2 + N2 * CV(K1)) * TX + xi]; });
-    int idx = 0;
-    sfor<0, N1>([&](auto K1) {
-      b[CV(K1)] = cmulc(b[CV(K1)], tw[idx]);
-      idx += j2;
-      if (idx >= N) idx -= N;
-    });
+    const float2* twt = tw + j2 * N1;
+    sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmulc(b[CV(K1)], twt[CV(K1)]); });
     dft<N1, +1>(b);
-    float2* col = colbase + ca * a.sW;
-    sfor<0, N1>([&](auto J1) { col[(j2 + N2 * CV(J1)) * plane] = b[CV(J1)]; });
+    float2* col = colbase + ca * a.sW + (long long)j2 * plane;
+    sfor<0, N1>([&](auto J1) { col[CV(J1) * zst] = b[CV(J1)]; });
   }
 }
 
@@ -473,10 +580,12 @@ struct SizeOps {
   LaunchKY ky;        // y axis
   LaunchKZ kz;        // z axis (nullptr: unsupported on z)
   int k1_lines;       // rows per K1 block
+  int n1, n2;         // split of the x/y passes (twiddle table layout)
+  int z1, z2;         // split of the z pass
 };
 
-constexpr int kTY = 8;   // columns per y-pass block
-constexpr int kTZ = 8;   // columns per z-pass block
+constexpr int kTY = CBS_TY;   // columns per y-pass block
+constexpr int kTZ = CBS_TZ;   // columns per z-pass block
 
 template <int N1, int N2>
 void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
@@ -509,9 +618,9 @@ void launch_kz(const CbsArgs& a, hipStream_t s) {
 }
 
 #define CBS_SIZE_XYZ(n, a1, a2, z1, z2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, XGeom<a1, a2>::LINES }
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, XGeom<a1, a2>::LINES, a1, a2, z1, z2 }
 #define CBS_SIZE_XY(n, a1, a2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, XGeom<a1, a2>::LINES }
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, XGeom<a1, a2>::LINES, a1, a2, 0, 0 }
 
 // registry, defined in the size translation units
 const SizeOps* find_size(int n);

@@ -79,3 +79,25 @@ def test_directional_finite_difference(device):
         Lm = focal_intensity(e - h * vt, p, r0, tol=1e-8, max_iter=20000).item()
     fd = (Lp - Lm) / (2 * h)
     assert abs(fd - dg) <= 1e-3 * abs(dg)
+
+
+def test_sphere64_design_slab_gradient_vs_oracle(device):
+    """The gradient case on the 64^3 sphere grid: seeded design slab, objective
+    |E(r0)|^2, GPU forward + adjoint + gradient against the FP64 oracle's
+    adjoint gradient over the slab."""
+    sc = scenes.sphere64()
+    eps = sc.eps_r.copy()
+    rng = np.random.default_rng(0)
+    sl = (slice(18, 24), slice(8, 56), slice(8, 56))
+    eps[sl] = np.clip(eps[sl] + rng.uniform(-0.25, 0.25, eps[sl].shape), 1.0, 2.1).astype(np.float32)
+    r0, lo, hi = (32, 32, 44), (8, 8, 18), (56, 56, 24)
+    g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
+    p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
+    p.set_permittivity(torch.from_numpy(eps).to(device))
+    E, s1 = p.solve(tol=1e-6, max_iter=4000)
+    Ea, s2 = p.adjoint(E_fwd=E, r0=r0, tol=1e-6, max_iter=4000)
+    grad = p.gradient(E, Ea, lo, hi, scale=2.0)
+    Eo, _ = oc.solve_forward(g, eps, tol=1e-9, max_iter=20000)
+    ga = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, Eo, r0), tol=1e-9, max_iter=20000)
+    gref = oc.gradient(g, Eo, ga.E_s, lo, hi, scale=2.0)
+    assert rel(grad.cpu().numpy(), gref) < 1e-3

@@ -373,3 +373,47 @@ def test_zone_plate_focus_and_slab():
     lo, hi = d.design_box
     assert int(np.prod([b - a for a, b in zip(lo, hi)])) == 2012430
     assert d.eps_r.min() >= 1.0 and d.eps_r.max() <= np.float32(2.1)
+
+
+def test_single_mode_closed_form_matches_fft_closed_form():
+    g = small_grid((7, 6, 8), pml=(0, 0, 0))
+    eps_c = complex(np.complex64(1.6 + 0.03j))
+    modes = [((1, 2, 3), [1.0, 0.5j, -0.2]), ((5, 0, 4), [0.1, -0.3, 0.7j]), ((0, 3, 0), [0.2j, 1.0, 0.0])]
+    z, y, x = np.meshgrid(np.arange(g.nz), np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    S = np.zeros((3,) + g.vshape, dtype=np.complex128)
+    for (kx, ky, kz), s in modes:
+        ph = np.exp(2j * math.pi * (kx * x / g.nx + ky * y / g.ny + kz * z / g.nz))
+        S += np.asarray(s)[:, None, None, None] * ph[None]
+    Ek, _ = closed.uniform_medium(g, eps_c, S, 6)
+    E = np.zeros_like(S)
+    for p, e in closed.uniform_medium_modes(g, eps_c, modes, 6):
+        ph = np.exp(1j * g.pitch * (p[0] * x + p[1] * y + p[2] * z))
+        E += e[:, None, None, None] * ph[None]
+    assert rel(E, Ek) < 1e-12
+
+
+def test_adjoint_gradient_fd_at_32_voxels():
+    """The gradient case at reduced size: sphere in a random design slab,
+    objective |E(r0)|^2, 32 voxels drawn with default_rng(1), FP64 central
+    differences (h = 1e-3) against the adjoint gradient."""
+    sc = scenes.sphere_scene(20, LAM / 6, 0.5e-6, 1.45, 1.0, (2, 2, 3), supersample=4)
+    g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
+    eps = sc.eps_r.astype(np.float64)
+    rng = np.random.default_rng(0)
+    eps[5:9, 2:-2, 2:-2] = np.clip(eps[5:9, 2:-2, 2:-2] + rng.uniform(-0.25, 0.25, (4, 16, 16)), 1.0, 2.1)
+    r0 = (10, 10, 15)
+    L0, res = oc.objective_of_eps(g, eps, r0, 1e-13, 40000)
+    E = oc.plane_wave(g) + res.E_s
+    adj = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, E, r0), tol=1e-13, max_iter=40000)
+    grad = oc.gradient(g, E, adj.E_s)
+    vox = np.random.default_rng(1).choice(4 * 16 * 16, size=32, replace=False)
+    h = 1e-3
+    for v in vox:
+        z, y, x = 5 + v // 256, 2 + (v // 16) % 16, 2 + v % 16
+        ep, em = eps.copy(), eps.copy()
+        ep[z, y, x] += h
+        em[z, y, x] -= h
+        Lp, _ = oc.objective_of_eps(g, ep, r0, 1e-13, 40000, res.E_s)
+        Lm, _ = oc.objective_of_eps(g, em, r0, 1e-13, 40000, res.E_s)
+        fd = (Lp - Lm) / (2 * h)
+        assert abs(grad[z, y, x] - fd) <= 1e-4 * max(abs(fd), 1e-4 * abs(grad).max())
