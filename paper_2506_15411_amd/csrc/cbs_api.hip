@@ -157,7 +157,7 @@ __global__ void k_state_init(DevState* st, double tol, int max_iter, int record)
     st->tol = tol;
     st->eta = INFINITY;
     st->record = record;
-    st->arrive = 0u;
+    st->pending = 0;
   }
 }
 
@@ -184,8 +184,9 @@ constexpr int kResThreads = 256;
 __global__ void __launch_bounds__(kResThreads)
 k_residual(const double* part, int nb, DevState* st, double* hist) {
   __shared__ double s0[kResThreads], s1[kResThreads];
-  if (st->done) return;
+  if (st->done || !st->pending) return;
   residual_finish<kResThreads>(part, nb, st, hist, s0, s1);
+  if (threadIdx.x == 0) st->pending = 0;
 }
 
 // E += sign * pol exp(i kb z)  (incident field)
@@ -298,8 +299,7 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   const SizeOps* ox = find_size(nx);
   if (!ox) return false;
   const long long N = (long long)nx * ny * nz;
-  const long long rows = (long long)ny * nz;
-  const long long k1b = (rows + ox->k1_lines - 1) / ox->k1_lines;
+  const long long k1b = 3LL * ((ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS) * nz;   // x-pass blocks
   const size_t c8 = sizeof(float2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -342,6 +342,8 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.ny = p->ny;
   a.nz = p->nz;
   a.nxp = p->nxp;
+  a.gx = p->nxp / kBrick;
+  a.gy = (p->ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS;
   a.px = p->pml[0];
   a.py = p->pml[1];
   a.pz = p->pml[2];
@@ -354,6 +356,7 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.twz = p->twz;
   a.phase = p->phase;
   a.partials = p->partials;
+  a.k1_blocks = p->k1_blocks;
   a.hist = p->hist;
   a.st = p->state;
   const double d2 = p->pitch * p->pitch;
@@ -391,9 +394,19 @@ int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
   p->oz->kz(a, p->stream);
   p->oy->ky(a, +1, p->stream);
   p->ox->k1(a, K1_ITER, p->stream);
-  if (!CBS_FOLD_RESIDUAL)
+  if (!CBS_LAG_RESIDUAL) {
     hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
                        p->k1_blocks, p->state, p->hist);
+  }
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// reduce the residual of the last enqueued iteration (a no-op when nothing is
+// pending), so the state copied to the host is current
+int enqueue_residual(cbs_plan_s* p) {
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
+                     p->k1_blocks, p->state, p->hist);
   HIP_LAUNCHED();
   return CBS_OK;
 }
@@ -456,6 +469,7 @@ int advance_solve(cbs_plan_s* p, int iters) {
     if (rc != CBS_OK) return rc;
   }
   A.enqueued += q;
+  if (int rc = enqueue_residual(p)) return rc;
   const int slot = (A.head + A.count) % cbs_plan_s::kRing;
   HIP_TRY(hipMemcpyAsync(&p->mirror[slot], p->state, sizeof(DevState), hipMemcpyDeviceToHost,
                          p->stream));
@@ -673,7 +687,7 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
   p->ox = find_size(nx);
   p->oy = find_size(ny);
   p->oz = find_size(nz);
-  p->k1_blocks = (int)(((long long)ny * nz + p->ox->k1_lines - 1) / p->ox->k1_lines);
+  p->k1_blocks = (int)(3LL * ((ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS) * nz);
   p->stream = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(workspace);
   p->W = reinterpret_cast<float2*>(base + L.W);
@@ -932,7 +946,7 @@ int cbs_time_passes(cbs_plan_t p, void* E_dev, int iters, float* ms_out) {
     HIP_TRY(hipEventRecord(p->evp[3], p->stream));
     p->ox->k1(a, K1_ITER, p->stream);
     HIP_TRY(hipEventRecord(p->evp[4], p->stream));
-    if (!CBS_FOLD_RESIDUAL)
+    if (!CBS_LAG_RESIDUAL)   // else the next y pass reduces it, as in a solve
       hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
                          p->k1_blocks, p->state, p->hist);
     HIP_LAUNCHED();

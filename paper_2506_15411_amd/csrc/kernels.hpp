@@ -44,26 +44,29 @@ enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
 
 constexpr int kHistCap = 1 << 16;
 
+// The spectral work field W is stored in bricks of 8 x-columns:
+//   W[c][z][x / 8][y][x % 8]   (row pitch padded to nxp = 8 * gx columns)
+// so a y-pass tile (8 columns x ny rows) is one contiguous block, a z-pass
+// column keeps 64-byte pieces, and 8 consecutive rows of an x-line form 512-byte
+// contiguous pieces.
+constexpr int kBrick = 8;
+
 // Tuning knobs (compile-time; the defaults are the measured best on gfx950)
-#ifndef CBS_K1_THREADS
-#define CBS_K1_THREADS 256   // target threads per x-pass block (rows per block follow)
-#endif
 #ifndef CBS_K1_PREFETCH
 #define CBS_K1_PREFETCH 2    // x-pass: 1 = load V0, 2 = load V0 and E_s before the inverse FFT
-#endif
-#ifndef CBS_TY
-#define CBS_TY 8             // columns per y-pass block
-#endif
-#ifndef CBS_TZ
-#define CBS_TZ 8             // columns per z-pass block
 #endif
 #ifndef CBS_Y_TW_GLOBAL
 #define CBS_Y_TW_GLOBAL 0    // y pass: read twiddles from global memory (frees LDS for a 4th block)
 #endif
-#ifndef CBS_FOLD_RESIDUAL
-#define CBS_FOLD_RESIDUAL 0  // 1: last x-pass block reduces the residual; its device-scope
-                             // fences write back the per-XCD L2s, which costs more than the
-                             // separate reduction launch on this part
+#ifndef CBS_K1_ROWS
+#define CBS_K1_ROWS 4        // x-pass: rows of one component per workgroup
+#endif
+#ifndef CBS_X_TW_GLOBAL
+#define CBS_X_TW_GLOBAL 0    // x pass: read twiddles from global memory instead of LDS
+#endif
+#ifndef CBS_LAG_RESIDUAL
+#define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
+                             // residual reduction (no separate launch per iteration)
 #endif
 
 // Device-resident solve state (lives in the workspace).
@@ -76,7 +79,7 @@ struct DevState {
   double eta;      // last relative update norm
   float2 amp[3];   // point-source amplitude (already scaled by d^2)
   int record;      // keep eta history
-  unsigned arrive; // x-pass blocks that have written their residual partials
+  int pending;     // the x pass wrote residual partials that are not reduced yet
 };
 
 // Fixed-order sum of the per-block partials, then the stopping rule.  Run by
@@ -124,11 +127,12 @@ __device__ __forceinline__ void residual_finish(const double* part, int nb, DevS
 }
 
 struct CbsArgs {
-  int nx, ny, nz, nxp;          // grid, padded row pitch of W
+  int nx, ny, nz, nxp;          // grid, padded row length of W (8 * gx)
+  int gx, gy;                   // x bricks (nxp / 8), 8-row groups (ceil(ny / 8))
   int px, py, pz;               // absorbing layer per side
   long long sW;                 // component stride of W  (nz * ny * nxp)
   long long sE;                 // component stride of E  (nz * ny * nx)
-  float2* W;                    // spectral work field [3][nz][ny][nxp]
+  float2* W;                    // spectral work field, bricked (see kBrick)
   float2* E;                    // E_s, caller layout [3][nz][ny][nx]
   const float2* V0;             // unshifted potential * d^2, [nz][ny][nx]
   const float2* twx;            // x split n1 x n2: twx[j2 n1 + k1] = exp(-2 pi i j2 k1 / nx)
@@ -138,6 +142,7 @@ struct CbsArgs {
   const float2* fin;            // FIELD source / Green input
   float2* fout;                 // Green output
   double* partials;             // 2 doubles per K1 block
+  int k1_blocks;                // number of K1 blocks (partials to reduce)
   double* hist;                 // residual history
   DevState* st;
   int src;                      // SrcKind
@@ -161,8 +166,8 @@ template <int N1, int N2>
 struct XGeom {
   static constexpr int N = N1 * N2;
   static constexpr int TM = cmax(N1, N2);
-  static constexpr int LINES = cmax(1, CBS_K1_THREADS / (3 * TM));
-  static constexpr int THREADS = round64(3 * LINES * TM);
+  static constexpr int LINES = CBS_K1_ROWS;
+  static constexpr int THREADS = round64(LINES * TM);
 };
 template <int N1, int N2, int TX>
 struct YGeom {
@@ -227,40 +232,53 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* red, doub
 // ---------------------------------------------------------------------------
 // K1: x-pass with the fused CBS update
 // ---------------------------------------------------------------------------
+// A workgroup transforms R consecutive rows (y0 .. y0+R-1) of one component
+// at one z.  W is read and written in place in its bricks: element x of row y
+// sits at brick x/8, offset 8 y + x%8, so the R rows of one brick form one
+// contiguous 64 R-byte piece.  The inverse transform, the update and the
+// forward transform share one LDS exchange buffer per row.
 template <int N1, int N2, int MODE>
 __global__ void __launch_bounds__((XGeom<N1, N2>::THREADS))
 k1_xpass(CbsArgs a) {
   using G = XGeom<N1, N2>;
-  constexpr int N = G::N, TM = G::TM, LINES = G::LINES;
-  __shared__ float2 lds[3 * LINES * N];
-  __shared__ float2 tw[N];
+  constexpr int N = G::N, TM = G::TM, R = G::LINES;
+  __shared__ float2 lds[R * N];     // R rows of one component, natural x order
   __shared__ double red[2 * (G::THREADS / 64)];
 
   if (MODE == K1_ITER && a.st->done) return;
 
   const int tid = threadIdx.x;
+#if CBS_X_TW_GLOBAL
+  const float2* tw = a.twx;
+#else
+  __shared__ float2 tw[N];
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
+#endif
+
+  // block -> (component, row group, z); the three components of the same rows
+  // are adjacent in the remapped order so V0 is shared in one L2
+  const unsigned L = xcd_remap(blockIdx.x, 3u * (unsigned)a.gy * (unsigned)a.nz);
+  const int c = (int)(L % 3u);
+  const unsigned rest = L / 3u;
+  const int yg = (int)(rest % (unsigned)a.gy);
+  const int z = (int)(rest / (unsigned)a.gy);
+  const int y0 = yg * R;
+  const int rv = (a.ny - y0) < R ? (a.ny - y0) : R;   // valid rows in this group
 
   const int t = tid % TM;
-  const int cl = tid / TM;
-  const int c = cl / LINES;
-  const int line = cl - c * LINES;
-  const long long nrows = (long long)a.ny * a.nz;
-  const long long row = (long long)blockIdx.x * LINES + line;
-  const bool ok = (cl < 3 * LINES) && (row < nrows);
-  const int cc = ok ? c : 0;
-  const long long rr = ok ? row : 0;
-  const int z = (int)(rr / a.ny);
-  const int y = (int)(rr - (long long)z * a.ny);
-  float2* L = lds + (cl < 3 * LINES ? cl : 0) * N;
-  float2* Wrow = a.W + cc * a.sW + rr * a.nxp;
-  const long long ebase = cc * a.sE + rr * a.nx;  // E / fin / fout row
-  const long long vbase = rr * a.nx;              // V0 row
-  __syncthreads();
+  const int line = tid / TM;
+  const bool ok = (line < rv);
+  const int y = y0 + (ok ? line : 0);
+  float2* Lr = lds + (line < R ? line : 0) * N;
+  // W bricks of this (component, z, row group): brick xt starts at wb + xt * ny * 8
+  float2* wb = a.W + c * a.sW + ((long long)z * a.gx * a.ny + y0) * kBrick;
+  const long long bstride = (long long)a.ny * kBrick;
+  const long long ebase = c * a.sE + ((long long)z * a.ny + y) * a.nx;  // E / fin / fout row
+  const long long vbase = ((long long)z * a.ny + y) * a.nx;             // V0 row
 
   float2 v[N2];  // thread t (< N1): element t + N1 m, m < N2
-  // optional early loads of the pointwise operands (their latency then hides
-  // behind the inverse transform)
+  // early loads of the pointwise operands (their latency hides behind the
+  // inverse transform)
   constexpr bool PF_V = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 1;
   constexpr bool PF_E = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 2;
   float2 pv[PF_V ? N2 : 1], pe[PF_E ? N2 : 1];
@@ -272,24 +290,29 @@ k1_xpass(CbsArgs a) {
   if constexpr (PF_E) {
     if (ok && t < N1) sfor<0, N2>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
   }
+
+  __syncthreads();   // the twiddle table is in LDS
+
+  // element x of this thread's row in the bricks
+  float2* wrow = wb + line * kBrick;
+  auto wat = [&](int x) -> float2& { return wrow[(x >> 3) * bstride + (x & 7)]; };
   if constexpr (MODE != K1_FWD) {
-    // inverse level A: thread j2 = t < N2, DFT-N1 over Wrow[j2 + N2 j1]
+    // inverse level A: thread j2 = t < N2, DFT-N1 over row[j2 + N2 j1]
     if (ok && t < N2) {
       float2 b[N1];
-      const float2* wt = Wrow + t;
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = wt[N2 * CV(J1)]; });
+      sfor<0, N1>([&](auto J1) { b[CV(J1)] = wat(t + N2 * CV(J1)); });
       dft<N1, +1>(b);
       const float2* twt = tw + t * N1;   // exp(-2 pi i t k1 / N), conjugated below
       sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmulc(b[CV(K1)], twt[CV(K1)]); });
-      sfor<0, N1>([&](auto K1) { L[t + N2 * CV(K1)] = b[CV(K1)]; });
+      sfor<0, N1>([&](auto K1) { Lr[t + N2 * CV(K1)] = b[CV(K1)]; });
     }
     __syncthreads();
-    // inverse level B: thread k1 = t < N1, DFT-N2 over L[N2 k1 + j2]
+    // inverse level B: thread k1 = t < N1, DFT-N2 over Lr[N2 k1 + j2]
     if (ok && t < N1) {
-      sfor<0, N2>([&](auto J2) { v[CV(J2)] = L[N2 * t + CV(J2)]; });
+      sfor<0, N2>([&](auto J2) { v[CV(J2)] = Lr[N2 * t + CV(J2)]; });
       dft<N2, +1>(v);
     }
-    __syncthreads();  // L is rewritten below
+    __syncthreads();  // lds is rewritten below
   }
 
   if constexpr (MODE == K1_INV) {
@@ -304,7 +327,7 @@ k1_xpass(CbsArgs a) {
     const bool yin = (y >= a.py) && (y < a.ny - a.py);
     const bool zin = (z >= a.pz) && (z < a.nz - a.pz);
     const float2 ph = a.phase[z];
-    const float2 pc = cc == 0 ? a.pol[0] : (cc == 1 ? a.pol[1] : a.pol[2]);
+    const float2 pc = c == 0 ? a.pol[0] : (c == 1 ? a.pol[1] : a.pol[2]);
     const float2 spl = cmul(ph, pc);  // pol_c exp(i kb z)
     sfor<0, N2>([&](auto M) {
       const int x = t + N1 * CV(M);
@@ -339,52 +362,27 @@ k1_xpass(CbsArgs a) {
         } else if (a.src == SRC_FIELD) {
           w = cadd(w, cscale(a.fin[ebase + x], a.src_scale));
         } else if (a.src == SRC_POINT) {
-          if (x == a.r0x && y == a.r0y && z == a.r0z) w = cadd(w, a.st->amp[cc]);
+          if (x == a.r0x && y == a.r0y && z == a.r0z) w = cadd(w, a.st->amp[c]);
         }
       }
       v[CV(M)] = w;
     });
-    // forward level A' (split N2 x N1): DFT-N2 over v, twiddle, to L[t + N1 k1']
+    // forward level A' (split N2 x N1): DFT-N2 over v, twiddle, to Lr[t + N1 k1']
     dft<N2, -1>(v);
     const float2* twc = tw + t;   // exp(-2 pi i t k / N) sits at [k][t] of the table
-    sfor<0, N2>([&](auto K) { L[t + N1 * CV(K)] = cmul(v[CV(K)], twc[N1 * CV(K)]); });
+    sfor<0, N2>([&](auto K) { Lr[t + N1 * CV(K)] = cmul(v[CV(K)], twc[N1 * CV(K)]); });
   }
   __syncthreads();
-  // forward level B': thread k1' = t < N2, DFT-N1 over L[N1 k1' + j2']
+  // forward level B': thread k1' = t < N2, DFT-N1 over Lr[N1 k1' + j2']
+  float2 bo[N1];
   if (ok && t < N2) {
-    float2 b[N1];
-    sfor<0, N1>([&](auto J) { b[CV(J)] = L[N1 * t + CV(J)]; });
-    dft<N1, -1>(b);
-    float2* wt = Wrow + t;
-    sfor<0, N1>([&](auto K) { wt[N2 * CV(K)] = b[CV(K)]; });
+    sfor<0, N1>([&](auto J) { bo[CV(J)] = Lr[N1 * t + CV(J)]; });
+    dft<N1, -1>(bo);
+    sfor<0, N1>([&](auto K) { wat(t + N2 * CV(K)) = bo[CV(K)]; });
   }
   if constexpr (MODE == K1_ITER) {
     block_sum2<G::THREADS>(sd, se, red, a.partials + 2 * (long long)blockIdx.x);
-#if CBS_FOLD_RESIDUAL
-    // the last block to arrive finishes the reduction: release this block's
-    // partials device-wide, count arrivals, acquire before reading the rest
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const unsigned prev = atomicAdd(&a.st->arrive, 1u);
-      last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last) {
-      __threadfence();
-      // all reads of lds ended before block_sum2's barrier: reuse it as scratch
-      constexpr bool kFits = sizeof(lds) >= 2 * G::THREADS * sizeof(double);
-      if constexpr (kFits) {
-        double* s0 = reinterpret_cast<double*>(lds);
-        residual_finish<G::THREADS>(a.partials, (int)gridDim.x, a.st, a.hist, s0,
-                                    s0 + G::THREADS);
-      } else {
-        __shared__ double s0[G::THREADS], s1[G::THREADS];
-        residual_finish<G::THREADS>(a.partials, (int)gridDim.x, a.st, a.hist, s0, s1);
-      }
-      if (threadIdx.x == 0) a.st->arrive = 0u;
-    }
-#endif
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.st->pending = 1;
   }
 }
 
@@ -404,6 +402,20 @@ ky_pass(CbsArgs a) {
 #endif
   if (a.st->done) return;
   const int tid = threadIdx.x;
+  if (CBS_LAG_RESIDUAL && S < 0 && blockIdx.x == 0 && a.st->pending) {
+    // finish the previous iteration's residual (stream order: the x pass that
+    // wrote the partials has completed); lds is still unused here
+    constexpr bool kFits = sizeof(lds) >= 2 * G::THREADS * sizeof(double);
+    if constexpr (kFits) {
+      double* s0 = reinterpret_cast<double*>(lds);
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, s0, s0 + G::THREADS);
+    } else {
+      __shared__ double s0[G::THREADS], s1[G::THREADS];
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, s0, s1);
+    }
+    if (tid == 0) a.st->pending = 0;
+    __syncthreads();
+  }
 #if !CBS_Y_TW_GLOBAL
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
 #endif
@@ -414,10 +426,12 @@ ky_pass(CbsArgs a) {
   const int bx = (int)(L % gx);
   const unsigned rest = L / gx;
   const int z = (int)(rest % (unsigned)a.nz), c = (int)(rest / (unsigned)a.nz);
+  static_assert(TX == kBrick, "y-pass tiles are one brick wide");
   const int x = bx * TX + xi;
   const bool xok = x < a.nx;
-  float2* col = a.W + c * a.sW + (long long)z * a.ny * a.nxp + (xok ? x : 0);
-  const long long ps = a.nxp;
+  // the tile is brick (c, z, bx): ny rows of 8 columns, contiguous
+  float2* col = a.W + c * a.sW + ((long long)z * a.gx + bx) * a.ny * kBrick + xi;
+  const long long ps = kBrick;
   __syncthreads();
   if (t < N2) {
     float2 b[N1];
@@ -465,12 +479,13 @@ kz_pass(CbsArgs a) {
   const int t = tid / TX;
   const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
   const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.ny);
-  const int bx = (int)(L % gx);
-  const int y = (int)(L / gx);
+  const int y = (int)(L % (unsigned)a.ny);   // rows y, y+1 of a brick share a 128-byte line
+  const int bx = (int)(L / (unsigned)a.ny);
   const int x = bx * TX + xi;
   const bool xok = x < a.nx;
-  const long long plane = (long long)a.ny * a.nxp;
-  float2* colbase = a.W + (long long)y * a.nxp + (xok ? x : 0);
+  static_assert(TX == kBrick, "z-pass tiles are one brick wide");
+  const long long plane = (long long)a.ny * a.nxp;   // z stride (gx bricks of ny x 8)
+  float2* colbase = a.W + ((long long)bx * a.ny + y) * kBrick + xi;
   __syncthreads();
 
   // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
@@ -579,19 +594,17 @@ struct SizeOps {
   LaunchK1 k1;        // x axis
   LaunchKY ky;        // y axis
   LaunchKZ kz;        // z axis (nullptr: unsupported on z)
-  int k1_lines;       // rows per K1 block
   int n1, n2;         // split of the x/y passes (twiddle table layout)
   int z1, z2;         // split of the z pass
 };
 
-constexpr int kTY = CBS_TY;   // columns per y-pass block
-constexpr int kTZ = CBS_TZ;   // columns per z-pass block
+constexpr int kTY = kBrick;   // columns per y-pass block
+constexpr int kTZ = kBrick;   // columns per z-pass block
 
 template <int N1, int N2>
 void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
   using G = XGeom<N1, N2>;
-  const long long rows = (long long)a.ny * a.nz;
-  const unsigned nb = (unsigned)((rows + G::LINES - 1) / G::LINES);
+  const unsigned nb = 3u * (unsigned)a.gy * (unsigned)a.nz;
   if (mode == K1_FWD)
     hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD>), dim3(nb), dim3(G::THREADS), 0, s, a);
   else if (mode == K1_ITER)
@@ -618,9 +631,9 @@ void launch_kz(const CbsArgs& a, hipStream_t s) {
 }
 
 #define CBS_SIZE_XYZ(n, a1, a2, z1, z2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, XGeom<a1, a2>::LINES, a1, a2, z1, z2 }
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, a1, a2, z1, z2 }
 #define CBS_SIZE_XY(n, a1, a2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, XGeom<a1, a2>::LINES, a1, a2, 0, 0 }
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, a1, a2, 0, 0 }
 
 // registry, defined in the size translation units
 const SizeOps* find_size(int n);
