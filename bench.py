@@ -175,9 +175,10 @@ def main(argv=None):
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="arrival rate as a fraction of the one-at-a-time service rate")
     ap.add_argument("--profile-iters", type=int, default=0,
-                    help="profiling mode: run this many CBS iterations of the workload "
-                         "(one launch of each pass per iteration) and a 1 GiB device copy "
-                         "used to calibrate memory counters; prints no JSON line")
+                    help="profiling mode: about 1 s of warm-up iterations, then this many "
+                         "CBS iterations of the workload (one launch of each pass per "
+                         "iteration) and a 1 GiB device copy used to calibrate memory "
+                         "counters; prints no JSON line")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -206,6 +207,9 @@ def main(argv=None):
 
     if args.profile_iters > 0:
         plan.set_permittivity(eps)
+        # about a second of iterations first, so clocks are at their working level
+        warm = max(1, int(1.0e3 / max(1e-3, sum(plan.time_passes(iters=2, E=E).values()))))
+        plan.time_passes(iters=warm, E=E)
         passes = plan.time_passes(iters=args.profile_iters, E=E)
         ms = copy_probe(dev)
         log(f"[bench] profile mode: {args.profile_iters} iterations of {sc.name}; "

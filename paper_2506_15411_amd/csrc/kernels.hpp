@@ -61,9 +61,6 @@ constexpr int kBrick = 8;
 #ifndef CBS_K1_ROWS
 #define CBS_K1_ROWS 4        // x-pass: rows of one component per workgroup
 #endif
-#ifndef CBS_X_TW_GLOBAL
-#define CBS_X_TW_GLOBAL 0    // x pass: read twiddles from global memory instead of LDS
-#endif
 #ifndef CBS_LAG_RESIDUAL
 #define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
                              // residual reduction (no separate launch per iteration)
@@ -248,12 +245,8 @@ k1_xpass(CbsArgs a) {
   if (MODE == K1_ITER && a.st->done) return;
 
   const int tid = threadIdx.x;
-#if CBS_X_TW_GLOBAL
-  const float2* tw = a.twx;
-#else
   __shared__ float2 tw[N];
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
-#endif
 
   // block -> (component, row group, z); the three components of the same rows
   // are adjacent in the remapped order so V0 is shared in one L2
@@ -488,10 +481,10 @@ kz_pass(CbsArgs a) {
   float2* colbase = a.W + ((long long)bx * a.ny + y) * kBrick + xi;
   __syncthreads();
 
+  const long long zst = (long long)N2 * plane;  // z stride between the samples of one DFT-N1
   // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
   const int ca = t / N2;
   const int j2 = t - ca * N2;
-  const long long zst = (long long)N2 * plane;  // uniform stride between a thread's z samples
   if (t < 3 * N2) {
     const float2* col = colbase + ca * a.sW + (long long)j2 * plane;
     float2 b[N1];
