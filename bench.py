@@ -85,6 +85,12 @@ def copy_probe(dev, nbytes=1 << 30, reps=1):
     return ms
 
 
+# iteration cap per served solve: high enough that every request of the served
+# stream reaches tol (the slowest, large high-index spheres on the 128^3 grid,
+# need about 5000-7000 iterations at tol 1e-4)
+SERVE_MAX_ITER = 20000
+
+
 def serving(dev, n_requests: int, load: float, tol: float):
     """Served stream of mixed-grid forward/adjoint solves (Poisson arrivals,
     numpy default_rng(0)): one-at-a-time service time measured first, then the
@@ -95,7 +101,7 @@ def serving(dev, n_requests: int, load: float, tol: float):
     from paper_2506_15411_amd.serve import Server, summarize
     trace = scenes.served_trace(n_requests, 1.0, seed=0)
     unit_arrivals = [r.arrival for r in trace]
-    srv = Server(dev, max_active=4, tol=tol, max_iter=4000)
+    srv = Server(dev, max_active=4, tol=tol, max_iter=SERVE_MAX_ITER)
 
     def prog(tag):
         def f(res, k):
@@ -123,7 +129,7 @@ def serving(dev, n_requests: int, load: float, tol: float):
         "requests": len(trace), "load": load, "arrival_rate_hz": round(rate, 3),
         "grids": ["64^3 lambda/6", "128^3 lambda/6", "192x192x256 lambda/12", "275x275x315 lambda/16"],
         "mean_service_s": round(service, 4),
-        "max_iter_per_solve": 4000,
+        "max_iter_per_solve": SERVE_MAX_ITER,
         "iterations_per_grid": {k: {"median": int(np.median(v)), "max": int(max(v))} for k, v in per.items()},
         "continuous_batching": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in mixed.items()},
         "one_at_a_time": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in seq.items()},

@@ -5,7 +5,8 @@ benchmark times (the same plans and kernels; only the inputs differ).
   single Fourier modes, whose every iterate has a closed form (checked at all
   voxels of sampled x, y and z lines and at random voxels), and two full CBS
   iterations of the 100 um lens against the FP64 oracle over the whole volume.
-* 275 x 275 x 315 (the 16 um lens): equal-iteration parity with the oracle.
+* 275 x 275 x 315 (the 16 um lens): equal-iteration parity with the oracle of
+  the forward field, and of the design-slab gradient (forward + adjoint).
 * The served grids (128^3, 192 x 192 x 256): one Green's-operator application.
 """
 
@@ -117,6 +118,30 @@ def test_lens16_equal_iterations_vs_oracle(device):
     res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=k)
     assert rel_chunked(E, res.E_s) < 1e-4
     p.close()
+
+
+def test_lens16_gradient_equal_iterations_vs_oracle(device):
+    """The adjoint-gradient pipeline at the 16 um lens size with its seeded design
+    slab: k forward iterations, the adjoint source conj(E(r0)) taken from that
+    iterate, k adjoint iterations, the gradient over the 2 um slab; the oracle
+    does the same in FP64."""
+    sc = scenes.zoneplate16_design(0)
+    k = 6
+    lo, hi = sc.design_box
+    p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
+    p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
+    E, s1 = p.solve(tol=0.0, max_iter=k)
+    Ea, s2 = p.adjoint(E_fwd=E, r0=sc.r0, tol=0.0, max_iter=k)
+    assert s1.iterations == k and s2.iterations == k
+    grad = p.gradient(E, Ea, lo, hi, scale=2.0).cpu().numpy().astype(np.float64)
+    p.close()
+    del E, Ea
+    g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
+    Eo, _ = oc.solve_forward(g, sc.eps_r, tol=0.0, max_iter=k)
+    ga = oc.solve_adjoint(g, sc.eps_r, oc.adjoint_point_source(g, Eo, sc.r0), tol=0.0, max_iter=k)
+    gref = oc.gradient(g, Eo, ga.E_s, lo, hi, scale=2.0)
+    assert grad.shape == gref.shape
+    assert np.linalg.norm(grad - gref) / np.linalg.norm(gref) < 1e-3
 
 
 @pytest.mark.parametrize("shape,pitch", [((128, 128, 128), LAM / 6), ((192, 192, 256), LAM / 12)])
