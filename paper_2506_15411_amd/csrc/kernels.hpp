@@ -18,14 +18,15 @@
 // (one per thread) and multiplies by exp(-+2 pi i j2 k1 / n); level B does
 // N1 DFT-N2 over the contiguous groups (one per thread).  Level A writes its
 // results to the LDS slots its inputs came from, so each exchange needs one
-// buffer and one barrier.  In K1 the inverse transform ends with thread t
-// holding GW[t + N1 m]; the forward transform of the next W is chosen with
-// the transposed split (DFT-N2 over exactly those elements first), so the
-// update and the start of the forward transform run in registers without an
-// LDS round trip.  In KZ the forward level B leaves each thread with all
-// z-frequencies k1 + N1 k2 of its group for the three components, the Green
-// multiply and the inverse level B run on those registers, and the z
-// spectrum is never reordered.
+// buffer and one barrier.  The inter-level twiddles come from an FP64-built
+// table stored [j2][k1], so each thread's twiddles are contiguous.  In K1 the
+// inverse transform ends with thread t holding GW[t + N1 m]; the forward
+// transform of the next W is chosen with the transposed split (DFT-N2 over
+// exactly those elements first), so the update and the start of the forward
+// transform run in registers without an LDS round trip.  In KZ the forward
+// level B leaves each thread with all z-frequencies k1 + N1 k2 of its group
+// for the three components, the Green multiply and the inverse level B run on
+// those registers, and the z spectrum is never reordered.
 //
 // Work is in units of the voxel pitch: lengths are scaled by 1/d, potentials
 // by d^2 (p d in [-pi, pi], kb^2 d^2, eps d^2), which leaves E_s unchanged.
@@ -45,10 +46,10 @@ enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
 constexpr int kHistCap = 1 << 16;
 
 // The spectral work field W is stored in bricks of 8 x-columns:
-//   W[c][z][x / 8][y][x % 8]   (row pitch padded to nxp = 8 * gx columns)
+//   W[c][z][x / 8][y][x % 8]   (x padded to nxp = 8 * gx columns)
 // so a y-pass tile (8 columns x ny rows) is one contiguous block, a z-pass
-// column keeps 64-byte pieces, and 8 consecutive rows of an x-line form 512-byte
-// contiguous pieces.
+// column of one brick row is a 64-byte piece per plane (rows y and y+1 share a
+// 128-byte line), and R consecutive rows of an x-line form 64 R-byte pieces.
 constexpr int kBrick = 8;
 
 // Tuning knobs (compile-time; the defaults are the measured best on gfx950)
@@ -125,7 +126,7 @@ __device__ __forceinline__ void residual_finish(const double* part, int nb, DevS
 
 struct CbsArgs {
   int nx, ny, nz, nxp;          // grid, padded row length of W (8 * gx)
-  int gx, gy;                   // x bricks (nxp / 8), 8-row groups (ceil(ny / 8))
+  int gx, gy;                   // x bricks (nxp / 8), x-pass row groups (ceil(ny / CBS_K1_ROWS))
   int px, py, pz;               // absorbing layer per side
   long long sW;                 // component stride of W  (nz * ny * nxp)
   long long sE;                 // component stride of E  (nz * ny * nx)
