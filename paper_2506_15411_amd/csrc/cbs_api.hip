@@ -299,7 +299,7 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   const SizeOps* ox = find_size(nx);
   if (!ox) return false;
   const long long N = (long long)nx * ny * nz;
-  const long long k1b = 3LL * ((ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS) * nz;   // x-pass blocks
+  const long long k1b = 3LL * ((ny + ox->k1_rows - 1) / ox->k1_rows) * nz;   // x-pass blocks
   const size_t c8 = sizeof(float2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -343,7 +343,7 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.nz = p->nz;
   a.nxp = p->nxp;
   a.gx = p->nxp / kBrick;
-  a.gy = (p->ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS;
+  a.gy = (p->ny + p->ox->k1_rows - 1) / p->ox->k1_rows;
   a.px = p->pml[0];
   a.py = p->pml[1];
   a.pz = p->pml[2];
@@ -687,7 +687,7 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
   p->ox = find_size(nx);
   p->oy = find_size(ny);
   p->oz = find_size(nz);
-  p->k1_blocks = (int)(3LL * ((ny + CBS_K1_ROWS - 1) / CBS_K1_ROWS) * nz);
+  p->k1_blocks = (int)(3LL * ((ny + p->ox->k1_rows - 1) / p->ox->k1_rows) * nz);
   p->stream = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(workspace);
   p->W = reinterpret_cast<float2*>(base + L.W);

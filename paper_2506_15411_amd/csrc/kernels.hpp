@@ -60,7 +60,10 @@ constexpr int kBrick = 8;
 #define CBS_Y_TW_GLOBAL 0    // y pass: read twiddles from global memory (frees LDS for a 4th block)
 #endif
 #ifndef CBS_K1_ROWS
-#define CBS_K1_ROWS 4        // x-pass: rows of one component per workgroup
+#define CBS_K1_ROWS 0        // x-pass: rows of one component per workgroup (0: per-size rule)
+#endif
+#ifndef CBS_KZ_TX
+#define CBS_KZ_TX 0          // z-pass: columns per workgroup, 8 or 4 (0: per-size rule)
 #endif
 #ifndef CBS_LAG_RESIDUAL
 #define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
@@ -126,7 +129,7 @@ __device__ __forceinline__ void residual_finish(const double* part, int nb, DevS
 
 struct CbsArgs {
   int nx, ny, nz, nxp;          // grid, padded row length of W (8 * gx)
-  int gx, gy;                   // x bricks (nxp / 8), x-pass row groups (ceil(ny / CBS_K1_ROWS))
+  int gx, gy;                   // x bricks (nxp / 8), x-pass row groups (ceil(ny / rows))
   int px, py, pz;               // absorbing layer per side
   long long sW;                 // component stride of W  (nz * ny * nxp)
   long long sE;                 // component stride of E  (nz * ny * nx)
@@ -160,11 +163,33 @@ struct CbsArgs {
 constexpr int cmax(int a, int b) { return a > b ? a : b; }
 constexpr int round64(int t) { return (t + 63) / 64 * 64; }
 
+// Rows per x-pass workgroup: TM threads serve one row.  The iteration kernel
+// needs about 200 VGPRs (two waves per SIMD), so workgroups of at most two
+// waves pack the CU fully; among R = 1..8 with R TM <= 128 pick the one whose
+// lanes fill their waves best, the larger R on ties (measured: 621 = 27 x 23
+// best at R = 4, 275 = 25 x 11 at R = 5; three-wave groups of R = 7 lose a
+// quarter of the occupancy and run 10% slower).
+constexpr int k1_rows_for(int tm) {
+  if (CBS_K1_ROWS > 0) return CBS_K1_ROWS;
+  int best = 1;
+  for (int r = 2; r <= 8 && r * tm <= 128; ++r)
+    if (r * tm * round64(best * tm) >= best * tm * round64(r * tm)) best = r;
+  return best;
+}
+// Columns per z-pass workgroup: a whole brick row (8) unless the exchange
+// buffer of 3 components x 8 columns would leave room for fewer than three
+// workgroups per CU (160 KB of LDS), then half a brick row (measured at
+// 315 = 35 x 9: 0.39 ms with 4 columns against 0.46 ms with 8).
+constexpr int kz_tx_for(int n) {
+  if (CBS_KZ_TX > 0) return CBS_KZ_TX;
+  return 3 * n * 8 * 8 + n * 8 <= 53 * 1024 ? 8 : 4;
+}
+
 template <int N1, int N2>
 struct XGeom {
   static constexpr int N = N1 * N2;
   static constexpr int TM = cmax(N1, N2);
-  static constexpr int LINES = CBS_K1_ROWS;
+  static constexpr int LINES = k1_rows_for(TM);
   static constexpr int THREADS = round64(LINES * TM);
 };
 template <int N1, int N2, int TX>
@@ -471,15 +496,19 @@ kz_pass(CbsArgs a) {
   for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
   const int xi = tid % TX;
   const int t = tid / TX;
-  const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
-  const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.ny);
-  const int y = (int)(L % (unsigned)a.ny);   // rows y, y+1 of a brick share a 128-byte line
-  const int bx = (int)(L / (unsigned)a.ny);
+  // remapped order: the kBrick / TX parts of one brick row, then y, then the
+  // brick; rows y, y+1 of a brick share a 128-byte line
+  static_assert(kBrick % TX == 0, "z-pass tiles split a brick row evenly");
+  constexpr int PARTS = kBrick / TX;
+  const unsigned L = xcd_remap(blockIdx.x, (unsigned)(a.nxp / TX) * (unsigned)a.ny);
+  const int part = (int)(L % PARTS);
+  const int y = (int)((L / PARTS) % (unsigned)a.ny);
+  const int brick = (int)(L / (PARTS * (unsigned)a.ny));
+  const int bx = brick * PARTS + part;      // tile index along x
   const int x = bx * TX + xi;
   const bool xok = x < a.nx;
-  static_assert(TX == kBrick, "z-pass tiles are one brick wide");
   const long long plane = (long long)a.ny * a.nxp;   // z stride (gx bricks of ny x 8)
-  float2* colbase = a.W + ((long long)bx * a.ny + y) * kBrick + xi;
+  float2* colbase = a.W + ((long long)brick * a.ny + y) * kBrick + part * TX + xi;
   __syncthreads();
 
   const long long zst = (long long)N2 * plane;  // z stride between the samples of one DFT-N1
@@ -590,10 +619,10 @@ struct SizeOps {
   LaunchKZ kz;        // z axis (nullptr: unsupported on z)
   int n1, n2;         // split of the x/y passes (twiddle table layout)
   int z1, z2;         // split of the z pass
+  int k1_rows;        // rows per x-pass workgroup when this length is the x axis
 };
 
 constexpr int kTY = kBrick;   // columns per y-pass block
-constexpr int kTZ = kBrick;   // columns per z-pass block
 
 template <int N1, int N2>
 void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
@@ -619,15 +648,19 @@ void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
 
 template <int N1, int N2>
 void launch_kz(const CbsArgs& a, hipStream_t s) {
-  using G = ZGeom<N1, N2, kTZ>;
-  dim3 grid((unsigned)((long long)((a.nx + kTZ - 1) / kTZ) * a.ny));
-  hipLaunchKernelGGL((kz_pass<N1, N2, kTZ>), grid, dim3(G::THREADS), 0, s, a);
+  constexpr int TX = kz_tx_for(N1 * N2);
+  using G = ZGeom<N1, N2, TX>;
+  dim3 grid((unsigned)((long long)(a.nxp / TX) * a.ny));
+  hipLaunchKernelGGL((kz_pass<N1, N2, TX>), grid, dim3(G::THREADS), 0, s, a);
 }
 
-#define CBS_SIZE_XYZ(n, a1, a2, z1, z2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, a1, a2, z1, z2 }
+#define CBS_SIZE_XYZ(n, a1, a2, z1, z2)                                                  \
+  SizeOps {                                                                              \
+    n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, &launch_kz<z1, z2>, a1, a2, z1, z2,       \
+        XGeom<a1, a2>::LINES                                                             \
+  }
 #define CBS_SIZE_XY(n, a1, a2) \
-  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, a1, a2, 0, 0 }
+  SizeOps { n, &launch_k1<a1, a2>, &launch_ky<a1, a2>, nullptr, a1, a2, 0, 0, XGeom<a1, a2>::LINES }
 
 // registry, defined in the size translation units
 const SizeOps* find_size(int n);
