@@ -417,3 +417,98 @@ def test_adjoint_gradient_fd_at_32_voxels():
         Lm, _ = oc.objective_of_eps(g, em, r0, 1e-13, 40000, res.E_s)
         fd = (Lp - Lm) / (2 * h)
         assert abs(grad[z, y, x] - fd) <= 1e-4 * max(abs(fd), 1e-4 * abs(grad).max())
+
+
+# ---------------------------------------------------------------------------
+# Mie series (continuum closed form for a dielectric sphere)
+# ---------------------------------------------------------------------------
+def test_mie_textbook_sample_calculation():
+    """Efficiencies of the textbook sample sphere (tests/golden, cited there)."""
+    from oracle import mie
+    with open(os.path.join(GOLDEN, "mie_bohren_huffman.json")) as f:
+        ref = json.load(f)
+    x = 2 * math.pi * ref["radius_um"] / ref["wavelength_um"]
+    qext, qsca, qback = mie.efficiencies(ref["m"], x)
+    assert qext == pytest.approx(ref["qext"], abs=1e-5)
+    assert qsca == pytest.approx(ref["qsca"], abs=1e-5)
+    assert qback == pytest.approx(ref["qback"], abs=1e-5)
+
+
+def test_mie_expansion_of_the_incident_wave():
+    """The same vector harmonics with j_n must sum to x^ exp(i k z)."""
+    from oracle import mie
+    k = 2 * math.pi / LAM
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(-3e-6, 3e-6, size=(3, 300))
+    c = (0.1e-6, -0.2e-6, 0.3e-6)
+    ref = np.zeros((3, 300), dtype=complex)
+    ref[0] = np.exp(1j * k * (pts[2] - c[2]))
+    rmax = np.sqrt(((pts - np.array(c)[:, None]) ** 2).sum(0)).max()
+    got = mie.incident_expansion(k, pts, c, mie.n_terms(k * rmax) + 10)
+    assert rel(got, ref) < 1e-9
+
+
+def test_mie_small_sphere_and_lossless_balance():
+    """Rayleigh limit a_1 -> -i (2/3) x^3 (m^2 - 1)/(m^2 + 2), b_1 = O(x^5);
+    a lossless sphere scatters all it extinguishes (optical theorem)."""
+    from oracle import mie
+    m, x = 1.45, 1e-2
+    a, b = mie.coefficients(m, x)
+    assert a[0] == pytest.approx(-1j * 2 / 3 * x ** 3 * (m * m - 1) / (m * m + 2), rel=1e-3)
+    assert abs(b[0]) < 1e-3 * abs(a[0])
+    for x in (0.5, 3.0, 7.09, 15.0):
+        qext, qsca, _ = mie.efficiencies(1.45, x)
+        assert qext == pytest.approx(qsca, rel=1e-10)
+
+
+def test_mie_far_field_carries_the_scattered_power():
+    """|E_s|^2 r^2 integrated over a large sphere equals Q_sca pi a^2 (the
+    scattered-field evaluation against the coefficient sum)."""
+    from oracle import mie
+    k = 2 * math.pi / LAM
+    a = 1.2e-6
+    qext, qsca, _ = mie.efficiencies(1.45, k * a)
+    R = 2000.0 / k
+    mu, wmu = np.polynomial.legendre.leggauss(64)
+    nphi = 48
+    phi = 2 * math.pi * np.arange(nphi) / nphi
+    MU, PHI = np.meshgrid(mu, phi, indexing="ij")
+    st = np.sqrt(1 - MU * MU)
+    pts = np.stack([R * st * np.cos(PHI), R * st * np.sin(PHI), R * MU]).reshape(3, -1)
+    Es = mie.scattered_field(k, a, 1.45, pts, (0.0, 0.0, 0.0))
+    I = (np.abs(Es) ** 2).sum(0).reshape(MU.shape) * R * R
+    csca = float((I * wmu[:, None]).sum() * (2 * math.pi / nphi))
+    assert csca / (math.pi * a * a) == pytest.approx(qsca, rel=2e-3)
+
+
+def test_cbs_sphere_field_approaches_mie():
+    """The converged CBS scattered field of the 64^3 sphere scene (n = 1.45,
+    R = 1.2 um, lambda/6) against the Mie series outside the sphere and the
+    absorbing layer, and the same box refined to lambda/10: the error is the
+    discretisation's (voxelised surface, finite layer) and must shrink."""
+    from oracle import mie
+    k = 2 * math.pi / LAM
+
+    def err(n, pitch, pml):
+        sc = scenes.sphere_scene(n, pitch, 1.2e-6, 1.45, 1.0, pml)
+        g = oc.Grid(*sc.shape, pitch, LAM, 1.0, sc.pml)
+        res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=1e-5, max_iter=20000)
+        nx, ny, nz = sc.shape
+        c = ((nx - 1) / 2 * pitch, (ny - 1) / 2 * pitch, (nz - 1) / 2 * pitch)
+        zz, yy, xx = np.meshgrid(np.arange(nz) * pitch, np.arange(ny) * pitch,
+                                 np.arange(nx) * pitch, indexing="ij")
+        r = np.sqrt((xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2)
+        px, py, pz = sc.pml
+        inner = np.zeros(r.shape, bool)
+        inner[pz + 2:nz - pz - 2, py + 2:ny - py - 2, px + 2:nx - px - 2] = True
+        sel = inner & (r > 1.2e-6 + pitch)
+        pts = np.stack([xx[sel], yy[sel], zz[sel]])
+        # the solver's incident phase is zero at z index 0, Mie's at the centre
+        Em = mie.scattered_field(k, 1.2e-6, 1.45, pts, c) * np.exp(1j * k * c[2])
+        Ec = np.stack([res.E_s[i][sel] for i in range(3)])
+        return rel(Ec, Em)
+
+    e6 = err(64, LAM / 6, (8, 8, 16))
+    e10 = err(107, LAM / 10, (13, 13, 27))
+    assert e6 < 0.15
+    assert e10 < 0.8 * e6
