@@ -182,6 +182,83 @@ def zone_plate_scene(shape, pitch, D: float, NA: float = 0.84, n_lens: float = 1
                            zones=len(radii)))
 
 
+# ---------------------------------------------------------------------------
+# Thickness-map lens design (optimisation paragraph, Fig. 2a)
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class LensDesign:
+    """Inputs of the thickness-map inverse design: the grid, where the lens
+    sits, the starting thickness map and the focus.  Thicknesses are in units
+    of the voxel pitch d; the lens occupies z in [z_lo, z_lo + h(x, y) d] with
+    z_lo = (z_base - 1/2) d (the lower face of voxel z_base)."""
+
+    name: str
+    shape: tuple              # (nx, ny, nz)
+    pitch: float
+    pml: tuple
+    z_base: int
+    h_max: float              # thickness bound (voxels): one 2 pi wrap, lambda0 / (n - n_bg)
+    n_lens: float
+    n_bg: float
+    D: float
+    NA: float
+    f_eff: float
+    r0: tuple                 # focal voxel (x, y, z)
+    aperture: np.ndarray      # [ny, nx] float32, 1 inside D/2 and the lateral interior
+    h_init: np.ndarray        # [ny, nx] float64, kinoform start (voxels)
+    sigma_vox: float          # Gaussian smoothing width (voxels)
+    lambda0: float = LAMBDA0
+
+    @property
+    def slab(self):
+        """z range [z0, z1) the lens can occupy."""
+        return self.z_base, self.z_base + int(math.ceil(self.h_max)) + 1
+
+
+def kinoform_design(shape, pitch, D: float, NA: float = 0.84, n_lens: float = 1.54,
+                    n_bg: float = 1.0, lambda0: float = LAMBDA0, pml=None,
+                    smoothing: float = 355e-9, name: str = "lens") -> LensDesign:
+    """A Fresnel (kinoform) lens of diameter D as the starting thickness map:
+    h = h_max (1 - frac(s)), s = (sqrt(r^2 + f^2) - f) / (lambda0 / n_bg), so
+    the optical path (n - n_bg) h + n_bg sqrt(r^2 + f^2) is constant modulo
+    lambda0, thickest at the centre, maximum thickness one wrap
+    lambda0 / (n - n_bg) (2.0 um at n = 1.54, the paper's starting lens).
+    r is measured from the lateral centre ((n - 1) / 2) d at voxel centres; the
+    base plane and focus follow the zone-plate conventions (exit face at the
+    maximum thickness)."""
+    nx, ny, nz = shape
+    if pml is None:
+        pml = pml_voxels(pitch, lambda0)
+    f = focal_length(D, NA)
+    hmax_m = lambda0 / (n_lens - n_bg)
+    y = (np.arange(ny) - (ny - 1) / 2.0) * pitch
+    x = (np.arange(nx) - (nx - 1) / 2.0) * pitch
+    r = np.sqrt(y[:, None] ** 2 + x[None, :] ** 2)
+    lat = np.zeros((ny, nx), dtype=bool)
+    lat[pml[1]:ny - pml[1], pml[0]:nx - pml[0]] = True
+    aperture = (r < D / 2.0) & lat
+    s = (np.sqrt(r * r + f * f) - f) / (lambda0 / n_bg)
+    h = np.where(aperture, hmax_m * (1.0 - (s - np.floor(s))), 0.0) / pitch
+    z_b = pml[2] + int(math.ceil(lambda0 / (2.0 * pitch)))
+    z_lo = (z_b - 0.5) * pitch
+    r0 = ((nx - 1) // 2, (ny - 1) // 2, int(math.floor((z_lo + hmax_m + f) / pitch + 0.5)))
+    return LensDesign(name=name, shape=tuple(shape), pitch=pitch, pml=tuple(pml), z_base=z_b,
+                      h_max=hmax_m / pitch, n_lens=n_lens, n_bg=n_bg, D=D, NA=NA, f_eff=f,
+                      r0=r0, aperture=aperture.astype(np.float32), h_init=h,
+                      sigma_vox=smoothing / pitch, lambda0=lambda0)
+
+
+def lens32_design() -> LensDesign:
+    """The optimisation benchmark: D = 32 um, NA 0.84, n = 1.54 on the
+    189 x 189 x 121 grid at 177 nm (benchmark paragraph)."""
+    return kinoform_design((189, 189, 121), 177e-9, 32e-6, name="lens32")
+
+
+def lens_design_small(n: int = 48, nz: int = 64, D: float = 5e-6) -> LensDesign:
+    """A small kinoform (n x n x nz at lambda/6) for parity tests of the design loop."""
+    return kinoform_design((n, n, nz), LAMBDA0 / 6, D, name=f"lens{n}")
+
+
 def design_slab(scene: Scene, thickness: float = 2.0e-6, seed: int = 0,
                 amp: float = 0.25, lo: float = 1.0, hi: float = 2.1) -> Scene:
     """Seed-random eps_r perturbation in a design slab above the lens base.
