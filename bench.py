@@ -142,6 +142,67 @@ def serving(dev, n_requests: int, load: float, tol: float):
     }
 
 
+def design_bench(args, dev):
+    """One JSON line for the thickness-map optimisation (optimisation and
+    benchmark paragraphs): W warm-up Adam steps, then K timed steps; value =
+    voxel-iterations of all forward and adjoint solves per second of wall time."""
+    import numpy as np
+    import torch
+    from paper_2506_15411_amd import scenes
+    from paper_2506_15411_amd.design import LensOptimizer
+    d = scenes.lens32_design()
+    nvox = int(np.prod(d.shape))
+    opt = LensOptimizer(d, dev, smoothing=not args.no_smoothing, tol=args.tol,
+                        max_iter=args.max_iter, check_every=args.check_every)
+    foms = []
+    for i in range(args.warmup):
+        st = opt.step()
+        foms.append(st.fom)
+        log(f"[bench] design warm-up {st.step}: |E(r0)|^2 {st.fom:.4e}, it {st.iterations}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for i in range(args.steps):
+        st = opt.step()
+        foms.append(st.fom)
+        iters += sum(st.iterations)
+        if st.step % 10 == 0 or i == args.steps - 1:
+            log(f"[bench] design step {st.step}: |E(r0)|^2 {st.fom:.4e} "
+                f"({st.fom / foms[0]:.3f} x start), it {st.iterations}, {st.seconds:.3f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    passes = opt.plan.time_passes(iters=10)
+    it_ms = sum(passes.values())
+    dom = max(PASS_BYTES, key=lambda k: passes[k])
+    achieved = PASS_BYTES[dom] * nvox / (passes[dom] * 1e-3) / 1e9
+    opt.close()
+    k = max(1, args.steps)
+    out = {
+        "metric": METRIC, "value": round(nvox * iters / dt / 1e9, 3), "unit": "Gvoxel-iter/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3 / k, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"lens32 {d.shape[0]}x{d.shape[1]}x{d.shape[2]} pitch 177 nm: "
+                               f"thickness-map Adam step (forward + adjoint CBS to tol "
+                               f"{args.tol:g}, gradient, design map), kinoform start D = 32 um "
+                               f"NA 0.84 n = 1.54",
+                   "voxels": nvox, "smoothing": not args.no_smoothing, "tol": args.tol,
+                   "iterations_per_step": iters / k},
+        "hbm_frac_iteration": round(ITER_BYTES * nvox / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "iteration_ms": round(it_ms, 4),
+        "passes_ms": {kk: round(v, 4) for kk, v in passes.items()},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": dom, "alg_bytes_per_launch": PASS_BYTES[dom] * nvox,
+                     "avg_launch_ms": round(passes[dom], 4)},
+        "design": {"fom_relative": [round(f / foms[0], 4) for f in foms],
+                   "paper_context_s_per_step": 3.7},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(sc):
     """FP64 oracle on the host: one CBS iteration of the same workload.
 
@@ -177,7 +238,11 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="zoneplate100",
-                    choices=["zoneplate100", "zoneplate16", "sphere64"])
+                    choices=["zoneplate100", "zoneplate16", "sphere64", "lens32"],
+                    help="lens32: the thickness-map optimisation of the 32 um kinoform "
+                         "(189 x 189 x 121 at 177 nm); a step is one Adam step")
+    ap.add_argument("--no-smoothing", action="store_true",
+                    help="lens32: optimise without the Gaussian smoothing filter")
     ap.add_argument("--tol", type=float, default=1e-4)
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--check-every", type=int, default=20)
@@ -207,6 +272,8 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    if args.workload == "lens32":
+        return design_bench(args, dev)
     log(f"[bench] building scene {args.workload}")
     sc = workload(args.workload)
     eps = torch.from_numpy(sc.eps_r).to(dev)

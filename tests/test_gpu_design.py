@@ -1,0 +1,81 @@
+"""GPU tests of the thickness-map lens design loop against the oracle's design
+map, chain rule and Adam step (oracle/design.py, FP64)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cbs as oc
+from oracle import design as od
+from paper_2506_15411_amd import scenes
+from paper_2506_15411_amd.design import DesignMap, LensOptimizer
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("smoothing", [False, True])
+def test_design_map_and_its_adjoint_match_oracle(smoothing, device):
+    """eps_r of the lens slab and the pull-back of a random dL/d eps_r at the
+    benchmark lens size (189 x 189 lateral)."""
+    d = scenes.lens32_design()
+    rng = np.random.default_rng(5)
+    ny, nx = d.aperture.shape
+    p = np.clip(d.h_init + rng.uniform(-0.4, 0.4, size=(ny, nx)), 0.0, d.h_max)
+    z0, z1 = d.slab
+    w = rng.normal(size=(z1 - z0, ny, nx))
+    m = DesignMap(d, device, smoothing)
+    pt = torch.tensor(p, dtype=torch.float32, device=device, requires_grad=True)
+    e = m(pt)
+    e.backward(torch.tensor(w, dtype=torch.float32, device=device))
+    e_ref = od.eps_of(p.astype(np.float32).astype(np.float64), d, smoothing)[z0:z1]
+    g_ref = od.grad_p(w, p.astype(np.float32).astype(np.float64), d, smoothing)
+    assert rel(e.detach().cpu().numpy(), e_ref) < 1e-6
+    assert rel(pt.grad.cpu().numpy(), g_ref) < 1e-5
+
+
+def test_design_gradient_and_first_step_match_oracle(device):
+    """One step of the loop on a small kinoform (48 x 48 x 64 at lambda/6):
+    |E(r0)|^2 and dL/dp from converged GPU solves against the oracle's
+    converged FP64 solves and chain rule, and the Adam update where the
+    gradient is not negligible (the first Adam step moves every such entry by
+    the step size along the gradient's sign)."""
+    d = scenes.lens_design_small()
+    opt = LensOptimizer(d, device, smoothing=True, tol=1e-7, max_iter=20000)
+    p0 = opt.p.detach().cpu().numpy().astype(np.float64)
+    st = opt.step()
+    g_gpu = opt.last_grad.cpu().numpy()
+    p1 = opt.p.detach().cpu().numpy().astype(np.float64)
+    opt.close()
+
+    g = oc.Grid(*d.shape, d.pitch, d.lambda0, d.n_bg, d.pml)
+    eps = od.eps_of(p0, d)
+    E, _ = oc.solve_forward(g, eps, tol=1e-11, max_iter=40000)
+    ix, iy, iz = d.r0
+    L = float(np.sum(np.abs(E[:, iz, iy, ix]) ** 2))
+    ga = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, E, d.r0), tol=1e-11, max_iter=40000)
+    z0, z1 = d.slab
+    nx, ny, _ = d.shape
+    geps = oc.gradient(g, E, ga.E_s, (0, 0, z0), (nx, ny, z1), scale=2.0)
+    g_ref = od.grad_p(geps, p0, d)
+    assert st.fom == pytest.approx(L, rel=1e-4)
+    assert rel(g_gpu, g_ref) < 1e-3
+    p_ref, _, _ = od.adam_step(p0, g_ref, np.zeros_like(p0), np.zeros_like(p0), 1, h_max=d.h_max)
+    big = np.abs(g_ref) > 1e-2 * np.abs(g_ref).max()
+    assert big.sum() > 50
+    assert np.allclose(p1[big], p_ref[big], atol=1e-5)
+
+
+def test_design_loop_warm_starts_and_improves(device):
+    """A few steps on the small kinoform: warm-started solves need fewer
+    iterations than the cold first step, and the focal intensity grows."""
+    d = scenes.lens_design_small()
+    opt = LensOptimizer(d, device, smoothing=True, tol=1e-5)
+    steps = [opt.step() for _ in range(6)]
+    opt.close()
+    assert sum(steps[-1].iterations) < sum(steps[0].iterations)
+    assert steps[-1].fom > steps[1].fom
