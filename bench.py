@@ -154,6 +154,23 @@ def design_bench(args, dev):
     nvox = int(np.prod(d.shape))
     opt = LensOptimizer(d, dev, smoothing=not args.no_smoothing, tol=args.tol,
                         max_iter=args.max_iter, check_every=args.check_every)
+    nx, ny, nz = d.shape
+    z0, z1 = d.slab
+    search = ((d.pml[0], d.pml[1], z1), (nx - d.pml[0], ny - d.pml[1], nz - d.pml[2]))
+
+    def figures():
+        # the field of the current design (the optimiser's last forward solve
+        # is at the previous p, so solve once more at p)
+        with torch.no_grad():
+            opt.eps[z0:z1] = opt.map(opt.p)
+        opt.plan.set_permittivity(opt.eps)
+        E, _ = opt.plan.solve(tol=args.tol, max_iter=args.max_iter, check_every=args.check_every)
+        f = opt.plan.lens_metrics(E, *search, aperture_m=d.D)
+        return {"eta_f": round(f["eta_f"], 4), "fwhm_um": [round(w * 1e6, 3) for w in f["fwhm"]],
+                "focus": list(f["focus"]), "peak": round(f["peak"], 3)}
+
+    start = figures()
+    log(f"[bench] design start: {start}")
     foms = []
     for i in range(args.warmup):
         st = opt.step()
@@ -171,6 +188,8 @@ def design_bench(args, dev):
                 f"({st.fom / foms[0]:.3f} x start), it {st.iterations}, {st.seconds:.3f} s")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    end = figures()
+    log(f"[bench] design end: {end}")
     passes = opt.plan.time_passes(iters=10)
     it_ms = sum(passes.values())
     dom = max(PASS_BYTES, key=lambda k: passes[k])
@@ -196,6 +215,7 @@ def design_bench(args, dev):
                      "kernel": dom, "alg_bytes_per_launch": PASS_BYTES[dom] * nvox,
                      "avg_launch_ms": round(passes[dom], 4)},
         "design": {"fom_relative": [round(f / foms[0], 4) for f in foms],
+                   "lens_start": start, "lens_end": end,
                    "paper_context_s_per_step": 3.7},
         "cpu_baseline": None,
     }

@@ -196,6 +196,39 @@ int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out);
 int cbs_gradient(cbs_plan_t plan, const void* E_dev, const void* E_adj_dev,
                  const int box_lo[3], const int box_hi[3], double scale, float* grad_dev);
 
+/* Lens figures of a field (focusing-efficiency paragraph: eta_f is the power in
+ * a disc of diameter three lateral FWHM at the focal plane over the incident
+ * power, reference [18]).  Readings: the focal point is the maximum of |E|^2
+ * (summed over components) in the search box; the FWHM are those of |E|^2
+ * along x and y in the focal plane and along z through the focus; the power
+ * through the disc (centred on the focus, voxel centres within the radius) is
+ * the flux of the Poynting vector S_z = Re(Ex conj(Hy) - Ey conj(Hx)) of the
+ * plane's propagating angular spectrum (H = k x E / k per plane wave, Ez from
+ * k . E = 0, evanescent components dropped; units where a plane wave of
+ * amplitude e0 carries |e0|^2), and the incident power is |e0|^2 pi (D/2)^2
+ * (plane wave on the aperture D in the same medium). */
+typedef struct {
+  int focus[3];        /* voxel (x, y, z) of the maximum of |E|^2 in the search box */
+  double peak;         /* |E|^2 there                                                */
+  double fwhm[3];      /* widths at half maximum along x, y in the focal plane and
+                          along z on the axis through the focus (metres; linear
+                          interpolation between voxels; NaN if a crossing is not
+                          inside the grid)                                           */
+  double disc_flux;    /* Poynting flux through the disc, m^2 x |e0|^2 (NaN if a
+                          lateral fwhm is)                                           */
+  double eta_f;        /* disc_flux / (|e0|^2 pi (D/2)^2) (NaN if a lateral fwhm is) */
+} cbs_lens_figures;
+
+/* Focus, FWHM and focusing efficiency of the complex64 field E_dev
+ * [3][nz][ny][nx] (normally the total field of a plane-wave solve).  The
+ * focus is searched in the half-open box [lo, hi) (x, y, z; ties go to the
+ * smaller linear index); the disc diameter is disc_factor times the mean of
+ * the x and y FWHM (3 in the paper); aperture_m is the lens diameter D and e0
+ * the incident amplitude.  Plane transforms and reductions are in FP64.
+ * Synchronises the plan's stream.  Uses the plan's workspace. */
+int cbs_lens_metrics(cbs_plan_t plan, const void* E_dev, const int lo[3], const int hi[3],
+                     double disc_factor, double aperture_m, double e0, cbs_lens_figures* out);
+
 /* One application of the Green's operator of the current medium:
  * out = F^-1 G^(p) F in  (complex64 fields; in and out may not alias).
  * Asynchronous on the plan's stream. */

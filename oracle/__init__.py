@@ -13,10 +13,11 @@ dense     dense 3N x 3N operator from explicit DFT matrices, LU and GMRES solves
 closed    closed forms: uniform-medium per-mode iteration, 1D slab reduction
 mie       Mie series of a dielectric sphere in a plane wave (continuum closed form)
 design    thickness-map lens design: eps_r(h), chain rule dL/dh, Adam step
+metrics   lens figures: focus, FWHM, focusing efficiency (Poynting flux)
 
 Every function cites the passage of the paper (arXiv 2506.15411) or of the CBS
 literature the paper builds on (its references [25] and [26]) that it follows.
 Where the paper is silent the reading taken is stated in the docstring.
 """
 
-from . import cbs, dense, closed, mie, design  # noqa: F401
+from . import cbs, dense, closed, mie, design, metrics  # noqa: F401

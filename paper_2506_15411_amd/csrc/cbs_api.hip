@@ -231,6 +231,166 @@ __global__ void k_gradient(const float2* E, const float2* Ea, long long sE, int 
   }
 }
 
+// ---------------------------------------------------------------------------
+// lens metrics: focus search, line profiles, disc power (FP64 reductions)
+// ---------------------------------------------------------------------------
+constexpr int kMetricBlocks = 256;
+constexpr int kMetricThreads = 256;
+
+__device__ __forceinline__ double intensity(const float2* E, long long sE, long long idx) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float2 e = E[c * sE + idx];
+    s += (double)e.x * (double)e.x + (double)e.y * (double)e.y;
+  }
+  return s;
+}
+
+// Per-block maximum of |E|^2 over a box with its linear voxel index; ties go
+// to the smaller index, so the result does not depend on the launch shape.
+__global__ void __launch_bounds__(kMetricThreads)
+k_argmax_intensity(const float2* E, long long sE, int nx, int ny, int x0, int y0, int z0, int bx,
+                   int by, int bz, double* part) {
+  __shared__ double sv[kMetricThreads];
+  __shared__ long long si[kMetricThreads];
+  double best = -1.0;
+  long long bi = 0x7fffffffffffffffLL;
+  const long long NB = (long long)bx * by * bz;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NB;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int xi = (int)(i % bx);
+    const long long r = i / bx;
+    const int yi = (int)(r % by);
+    const int zi = (int)(r / by);
+    const long long idx = ((long long)(z0 + zi) * ny + (y0 + yi)) * nx + (x0 + xi);
+    const double s = intensity(E, sE, idx);
+    if (s > best || (s == best && idx < bi)) {
+      best = s;
+      bi = idx;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = kMetricThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double v = sv[threadIdx.x + o];
+      const long long j = si[threadIdx.x + o];
+      if (v > sv[threadIdx.x] || (v == sv[threadIdx.x] && j < si[threadIdx.x])) {
+        sv[threadIdx.x] = v;
+        si[threadIdx.x] = j;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sv[0];
+    part[2 * blockIdx.x + 1] = (double)si[0];
+  }
+}
+
+// |E|^2 along the x, y and z lines through (fx, fy, fz): out[0, nx) then
+// out[nx, nx + ny) then out[nx + ny, nx + ny + nz).
+__global__ void k_line_intensity(const float2* E, long long sE, int nx, int ny, int nz, int fx,
+                                 int fy, int fz, double* out) {
+  const int n = nx + ny + nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int x = fx, y = fy, z = fz;
+    if (i < nx) x = i;
+    else if (i < nx + ny) y = i - nx;
+    else z = i - nx - ny;
+    out[i] = intensity(E, sE, ((long long)z * ny + y) * nx + x);
+  }
+}
+
+// The transverse field of plane fz in FP64: ex, ey [ny][nx].
+__global__ void k_plane_extract(const float2* E, long long sE, int nx, int ny, int fz,
+                                double2* ex, double2* ey) {
+  const long long NP = (long long)nx * ny;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * blockDim.x) {
+    const float2 a = E[(long long)fz * NP + i], b = E[sE + (long long)fz * NP + i];
+    ex[i] = make_double2(a.x, a.y);
+    ey[i] = make_double2(b.x, b.y);
+  }
+}
+
+// One pass of a plane DFT in FP64, out-of-place: along x (axis 0) or y
+// (axis 1) of an [ny][nx] plane, out[k] = sum_j in[j] w^(sign j k), with
+// w = tw[m] = exp(-2 pi i m / n) (sign -1: forward, +1: inverse, unscaled).
+// Direct sums: the planes are small and this runs once per measurement.
+__global__ void k_plane_dft(const double2* in, double2* out, int nx, int ny, int axis, int sign,
+                            const double2* tw) {
+  const long long NP = (long long)nx * ny;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    const int n = axis == 0 ? nx : ny;
+    const int k = axis == 0 ? x : y;
+    double re = 0.0, im = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const double2 v = axis == 0 ? in[(long long)y * nx + j] : in[(long long)j * nx + x];
+      const double2 w = tw[(int)(((long long)j * k) % n)];
+      const double wi = sign < 0 ? w.y : -w.y;
+      re += v.x * w.x - v.y * wi;
+      im += v.x * wi + v.y * w.x;
+    }
+    out[i] = make_double2(re, im);
+  }
+}
+
+// Angular spectrum of the transverse field -> propagating part of E and the
+// magnetic field in units where a plane wave has H = z x E:
+//   kz = sqrt(k^2 - kx^2 - ky^2) (evanescent components dropped),
+//   Ez = -(kx Ex + ky Ey) / kz,  H = k_vec x E / k.
+__global__ void k_angular_h(double2* ax, double2* ay, double2* hx, double2* hy, int nx, int ny,
+                            double dkx, double dky, double k) {
+  const long long NP = (long long)nx * ny;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i % nx), iy = (int)(i / nx);
+    const double kx = dkx * (ix < (nx + 1) / 2 ? ix : ix - nx);
+    const double ky = dky * (iy < (ny + 1) / 2 ? iy : iy - ny);
+    const double kz2 = k * k - kx * kx - ky * ky;
+    if (kz2 <= 0.0) {
+      ax[i] = ay[i] = hx[i] = hy[i] = make_double2(0.0, 0.0);
+      continue;
+    }
+    const double kz = sqrt(kz2);
+    const double2 ex = ax[i], ey = ay[i];
+    const double2 ez = make_double2(-(kx * ex.x + ky * ey.x) / kz, -(kx * ex.y + ky * ey.y) / kz);
+    hx[i] = make_double2((ky * ez.x - kz * ey.x) / k, (ky * ez.y - kz * ey.y) / k);
+    hy[i] = make_double2((kz * ex.x - kx * ez.x) / k, (kz * ex.y - kx * ez.y) / k);
+  }
+}
+
+// Per-block sums of S_z = Re(Ex conj(Hy) - Ey conj(Hx)) (times scale) over the
+// voxels of the plane whose centres lie within sqrt(r2) voxels of (cx, cy).
+__global__ void __launch_bounds__(kMetricThreads)
+k_disc_flux(const double2* ex, const double2* ey, const double2* hx, const double2* hy, int nx,
+            int ny, double cx, double cy, double r2, double scale, double* part) {
+  __shared__ double sh[kMetricThreads];
+  double acc = 0.0;
+  const long long NP = (long long)nx * ny;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < NP;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % nx), y = (int)(i / nx);
+    const double dx = x - cx, dy = y - cy;
+    if (dx * dx + dy * dy <= r2) {
+      const double2 a = ex[i], b = ey[i], u = hx[i], v = hy[i];
+      acc += (a.x * v.x + a.y * v.y) - (b.x * u.x + b.y * u.y);
+    }
+  }
+  sh[threadIdx.x] = acc * scale;
+  __syncthreads();
+  for (int o = kMetricThreads / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
 // streaming copy: one float4 per thread over a grid that covers the buffer
 // (the fastest plain copy form measured on this part)
 constexpr int kCopyThreads = 256;
@@ -259,7 +419,7 @@ struct cbs_plan_s {
   hipStream_t stream;
   // workspace carve-up
   float2 *W, *V0, *twx, *twy, *twz, *phase;
-  double *partials, *setup_part, *hist;
+  double *partials, *setup_part, *hist, *metrics;
   DevState* state;
   bool have_eps;
   double eps;  // 1/m^2
@@ -288,7 +448,7 @@ struct cbs_plan_s {
 namespace {
 
 struct Layout {
-  size_t W, V0, twx, twy, twz, phase, partials, setup, hist, state, total;
+  size_t W, V0, twx, twy, twz, phase, partials, setup, hist, metrics, state, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -316,6 +476,8 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   L.partials = take((size_t)2 * k1b * sizeof(double));
   L.setup = take((size_t)2 * kSetupBlocks * sizeof(double));
   L.hist = take((size_t)kHistCap * sizeof(double));
+  L.metrics = take((size_t)(2 * kMetricBlocks + nx + ny + nz + 1) * sizeof(double) +
+                   (size_t)(nx + ny + 5 * N / nz) * sizeof(double2));
   L.state = take(sizeof(DevState));
   L.total = off;
   return true;
@@ -699,6 +861,7 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
   p->partials = reinterpret_cast<double*>(base + L.partials);
   p->setup_part = reinterpret_cast<double*>(base + L.setup);
   p->hist = reinterpret_cast<double*>(base + L.hist);
+  p->metrics = reinterpret_cast<double*>(base + L.metrics);
   p->state = reinterpret_cast<DevState*>(base + L.state);
   p->have_eps = false;
   p->eps = -1.0;
@@ -901,6 +1064,123 @@ int cbs_gradient(cbs_plan_t p, const void* E, const void* Ea, const int lo[3], c
                      (long long)p->nx * p->ny * p->nz, p->nx, p->ny, lo[0], lo[1], lo[2], bx, by,
                      bz, scale * p->k0 * p->k0, grad);
   HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+namespace {
+// Full width at half maximum of the profile v[0, n) around its sample i0, with
+// the half-maximum crossings interpolated linearly between samples; NaN when
+// the profile does not fall below half on both sides inside [0, n).
+double fwhm_of(const double* v, int n, int i0, double pitch) {
+  const double half = 0.5 * v[i0];
+  int l = i0;
+  while (l > 0 && v[l - 1] >= half) --l;
+  int r = i0;
+  while (r < n - 1 && v[r + 1] >= half) ++r;
+  if (l == 0 || r == n - 1) return std::nan("");
+  const double xl = (l - 1) + (half - v[l - 1]) / (v[l] - v[l - 1]);
+  const double xr = r + (v[r] - half) / (v[r] - v[r + 1]);
+  return (xr - xl) * pitch;
+}
+}  // namespace
+
+int cbs_lens_metrics(cbs_plan_t p, const void* E, const int lo[3], const int hi[3],
+                     double disc_factor, double aperture_m, double e0, cbs_lens_figures* out) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!E || !lo || !hi || !out) return fail(CBS_E_INVALID, "NULL argument");
+  if (!(disc_factor > 0) || !(aperture_m > 0) || !(e0 > 0))
+    return fail(CBS_E_INVALID, "disc_factor, aperture and e0 must be > 0");
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || hi[a] > dims[a] || lo[a] >= hi[a])
+      return fail(CBS_E_INVALID, "search box axis %d [%d,%d) empty or outside [0,%d)", a, lo[a],
+                  hi[a], dims[a]);
+  const float2* F = static_cast<const float2*>(E);
+  const long long sE = (long long)p->nx * p->ny * p->nz;
+  const int bx = hi[0] - lo[0], by = hi[1] - lo[1], bz = hi[2] - lo[2];
+  const long long NB = (long long)bx * by * bz;
+  const int nb = (int)std::min<long long>(kMetricBlocks, (NB + kMetricThreads - 1) / kMetricThreads);
+  // 1. focus: the maximum of |E|^2 in the box
+  hipLaunchKernelGGL(k_argmax_intensity, dim3(nb), dim3(kMetricThreads), 0, p->stream, F, sE,
+                     p->nx, p->ny, lo[0], lo[1], lo[2], bx, by, bz, p->metrics);
+  HIP_LAUNCHED();
+  std::vector<double> part(2 * kMetricBlocks);
+  HIP_TRY(hipMemcpyAsync(part.data(), p->metrics, 2 * nb * sizeof(double), hipMemcpyDeviceToHost,
+                         p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double best = -1.0;
+  long long bi = 0;
+  for (int b = 0; b < nb; ++b)
+    if (part[2 * b] > best || (part[2 * b] == best && (long long)part[2 * b + 1] < bi)) {
+      best = part[2 * b];
+      bi = (long long)part[2 * b + 1];
+    }
+  const int fx = (int)(bi % p->nx), fy = (int)((bi / p->nx) % p->ny), fz = (int)(bi / ((long long)p->nx * p->ny));
+  // 2. profiles through the focus and their widths
+  const int nl = p->nx + p->ny + p->nz;
+  double* lines = p->metrics + 2 * kMetricBlocks;
+  hipLaunchKernelGGL(k_line_intensity, dim3((nl + 255) / 256), dim3(256), 0, p->stream, F, sE,
+                     p->nx, p->ny, p->nz, fx, fy, fz, lines);
+  HIP_LAUNCHED();
+  std::vector<double> prof(nl);
+  HIP_TRY(hipMemcpyAsync(prof.data(), lines, nl * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  out->focus[0] = fx;
+  out->focus[1] = fy;
+  out->focus[2] = fz;
+  out->peak = best;
+  out->fwhm[0] = fwhm_of(prof.data(), p->nx, fx, p->pitch);
+  out->fwhm[1] = fwhm_of(prof.data() + p->nx, p->ny, fy, p->pitch);
+  out->fwhm[2] = fwhm_of(prof.data() + p->nx + p->ny, p->nz, fz, p->pitch);
+  // 3. power through the disc of diameter disc_factor x lateral FWHM: the
+  // Poynting flux of the plane's propagating angular spectrum
+  out->disc_flux = std::nan("");
+  out->eta_f = std::nan("");
+  if (std::isfinite(out->fwhm[0]) && std::isfinite(out->fwhm[1])) {
+    const int nx = p->nx, ny = p->ny;
+    const long long NP = (long long)nx * ny;
+    double2* twx = reinterpret_cast<double2*>(lines + ((nl + 1) & ~1));   // 16-byte aligned
+    double2* twy = twx + nx;
+    double2* pl[5];
+    for (int k = 0; k < 5; ++k) pl[k] = twy + ny + k * NP;
+    std::vector<double2> t(nx + ny);
+    for (int m = 0; m < nx; ++m) t[m] = make_double2(std::cos(2 * M_PI * m / nx), -std::sin(2 * M_PI * m / nx));
+    for (int m = 0; m < ny; ++m) t[nx + m] = make_double2(std::cos(2 * M_PI * m / ny), -std::sin(2 * M_PI * m / ny));
+    HIP_TRY(hipMemcpyAsync(twx, t.data(), (nx + ny) * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+    const dim3 g((unsigned)std::min<long long>(4096, (NP + 255) / 256)), b(256);
+    // pl[0] = Ex, pl[1] = Ey, pl[4] scratch; forward 2D DFTs in place via scratch
+    hipLaunchKernelGGL(k_plane_extract, g, b, 0, p->stream, F, sE, nx, ny, fz, pl[0], pl[1]);
+    HIP_LAUNCHED();
+    auto dft2 = [&](double2* f, int sign) -> int {
+      hipLaunchKernelGGL(k_plane_dft, g, b, 0, p->stream, f, pl[4], nx, ny, 0, sign, twx);
+      HIP_LAUNCHED();
+      hipLaunchKernelGGL(k_plane_dft, g, b, 0, p->stream, pl[4], f, nx, ny, 1, sign, twy);
+      HIP_LAUNCHED();
+      return CBS_OK;
+    };
+    if ((rc = dft2(pl[0], -1)) || (rc = dft2(pl[1], -1))) return rc;
+    const double k = 2.0 * M_PI * p->n_bg / p->lambda0;
+    hipLaunchKernelGGL(k_angular_h, g, b, 0, p->stream, pl[0], pl[1], pl[2], pl[3], nx, ny,
+                       2.0 * M_PI / (nx * p->pitch), 2.0 * M_PI / (ny * p->pitch), k);
+    HIP_LAUNCHED();
+    for (int q = 0; q < 4; ++q)
+      if ((rc = dft2(pl[q], +1))) return rc;
+    const double radius = 0.5 * disc_factor * 0.5 * (out->fwhm[0] + out->fwhm[1]) / p->pitch;
+    const int nd = (int)std::min<long long>(kMetricBlocks, (NP + kMetricThreads - 1) / kMetricThreads);
+    const double scale = 1.0 / ((double)NP * (double)NP);   // two unscaled inverse transforms
+    hipLaunchKernelGGL(k_disc_flux, dim3(nd), dim3(kMetricThreads), 0, p->stream, pl[0], pl[1],
+                       pl[2], pl[3], nx, ny, (double)fx, (double)fy, radius * radius, scale,
+                       p->metrics);
+    HIP_LAUNCHED();
+    HIP_TRY(hipMemcpyAsync(part.data(), p->metrics, nd * sizeof(double), hipMemcpyDeviceToHost,
+                           p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    double sum = 0.0;
+    for (int q = 0; q < nd; ++q) sum += part[q];
+    out->disc_flux = sum * p->pitch * p->pitch;
+    out->eta_f = out->disc_flux / (e0 * e0 * M_PI * 0.25 * aperture_m * aperture_m);
+  }
   return CBS_OK;
 }
 

@@ -47,6 +47,12 @@ class cbs_stats(ctypes.Structure):
                 ("ms", ctypes.c_float)]
 
 
+class cbs_lens_figures(ctypes.Structure):
+    _fields_ = [("focus", ctypes.c_int * 3), ("peak", ctypes.c_double),
+                ("fwhm", ctypes.c_double * 3), ("disc_flux", ctypes.c_double),
+                ("eta_f", ctypes.c_double)]
+
+
 class cbs_source(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("pol", (ctypes.c_double * 2) * 3),
                 ("field", ctypes.c_void_p), ("r0", ctypes.c_int * 3),
@@ -65,7 +71,7 @@ SYMBOLS = [
     "cbs_plan_workspace_bytes", "cbs_axis_supported", "cbs_plan_create",
     "cbs_plan_set_pml_profile", "cbs_plan_set_shift_factor", "cbs_set_permittivity", "cbs_solve", "cbs_adjoint_solve",
     "cbs_solve_begin", "cbs_solve_advance", "cbs_solve_poll", "cbs_solve_end", "cbs_batch_step",
-    "cbs_gradient", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
+    "cbs_gradient", "cbs_lens_metrics", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
     "cbs_last_error",
 ]
 
@@ -112,6 +118,9 @@ def load(path: str | None = None):
     lib.cbs_gradient.argtypes = [c_void_p, c_void_p, c_void_p, P(c_int), P(c_int), c_double,
                                  c_void_p]
     lib.cbs_gradient.restype = c_int
+    lib.cbs_lens_metrics.argtypes = [c_void_p, c_void_p, P(c_int), P(c_int), c_double, c_double,
+                                     c_double, P(cbs_lens_figures)]
+    lib.cbs_lens_metrics.restype = c_int
     lib.cbs_apply_green.argtypes = [c_void_p, c_void_p, c_void_p]
     lib.cbs_apply_green.restype = c_int
     lib.cbs_time_passes.argtypes = [c_void_p, c_void_p, c_int, P(ctypes.c_float)]
@@ -227,6 +236,14 @@ def cbs_gradient(plan, E_ptr, E_adj_ptr, box_lo, box_hi, scale, grad_ptr):
     return check(load().cbs_gradient(plan, ctypes.c_void_p(E_ptr), ctypes.c_void_p(E_adj_ptr),
                                      _ints3(box_lo), _ints3(box_hi), float(scale),
                                      ctypes.c_void_p(grad_ptr)))
+
+
+def cbs_lens_metrics(plan, E_ptr, lo, hi, disc_factor, aperture_m, e0=1.0):
+    out = cbs_lens_figures()
+    check(load().cbs_lens_metrics(plan, ctypes.c_void_p(E_ptr), _ints3(lo), _ints3(hi),
+                                  float(disc_factor), float(aperture_m), float(e0),
+                                  ctypes.byref(out)))
+    return out
 
 
 def cbs_apply_green(plan, in_ptr, out_ptr):

@@ -193,6 +193,15 @@ class Plan:
         self._async_keep = None
         return _stats(rc, st)
 
+    def lens_metrics(self, E: torch.Tensor, lo, hi, aperture_m: float, disc_factor: float = 3.0,
+                     e0: float = 1.0) -> dict:
+        """Focus (maximum of |E|^2 in [lo, hi)), FWHM along x, y, z (metres) and the
+        focusing efficiency of the field E (see cbs_lens_metrics)."""
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        f = L.cbs_lens_metrics(self.handle, E.data_ptr(), lo, hi, disc_factor, aperture_m, e0)
+        return {"focus": tuple(f.focus), "peak": f.peak, "fwhm": tuple(f.fwhm),
+                "disc_flux": f.disc_flux, "eta_f": f.eta_f}
+
     def gradient(self, E: torch.Tensor, E_adj: torch.Tensor, box_lo=None, box_hi=None,
                  scale=2.0, out: torch.Tensor | None = None):
         """scale * k0^2 * Re(sum_c E_adj,c E_c) over [box_lo, box_hi) -> [z, y, x] float32."""

@@ -125,3 +125,75 @@ def test_adam_step_matches_torch():
         q.grad = torch.tensor(gr)
         opt.step()
     assert np.allclose(p, q.detach().numpy(), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Lens figures (focus, FWHM, focusing efficiency)
+# ---------------------------------------------------------------------------
+def test_fwhm_of_a_sampled_gaussian():
+    """FWHM of exp(-x^2 / (2 s^2)) is 2 sqrt(2 ln 2) s; linear interpolation
+    between samples at pitch s/5 is good to a few 1e-3."""
+    from oracle import metrics as om
+    s, d = 1.0, 0.2
+    x = (np.arange(201) - 97.3) * d
+    v = np.exp(-x * x / (2 * s * s))
+    w = om.fwhm(v, int(np.argmax(v)), d)
+    assert w == pytest.approx(2 * math.sqrt(2 * math.log(2)) * s, rel=3e-3)
+    assert math.isnan(om.fwhm(np.ones(10), 5, d))
+
+
+def test_plane_flux_of_plane_waves():
+    """A plane wave of unit amplitude carries S_z = cos(theta) through a plane:
+    normal incidence (x-polarised) and an oblique TM wave whose kx is a grid
+    frequency, E = (cos t, 0, -sin t) exp(i k (x sin t + z cos t)) sampled in
+    the plane z = 0 (only its transverse part enters)."""
+    from oracle import metrics as om
+    nx, ny, d = 64, 48, 0.1
+    k = 2 * math.pi / 0.75
+    x = np.arange(nx) * d
+    Ex = np.ones((ny, nx), dtype=complex)
+    Ey = np.zeros((ny, nx), dtype=complex)
+    assert np.allclose(om.plane_flux(Ex, Ey, d, k), 1.0, atol=1e-12)
+    m = 5
+    kx = 2 * math.pi * m / (nx * d)
+    t = math.asin(kx / k)
+    Ex = np.broadcast_to(math.cos(t) * np.exp(1j * kx * x)[None, :], (ny, nx)).copy()
+    assert np.allclose(om.plane_flux(Ex, Ey, d, k), math.cos(t), atol=1e-12)
+    # an evanescent component carries nothing
+    kx2 = 2 * math.pi * 20 / (nx * d)
+    assert kx2 > k
+    Ex2 = np.broadcast_to(np.exp(1j * kx2 * x)[None, :], (ny, nx)).copy()
+    assert np.allclose(om.plane_flux(Ex2, Ey, d, k), 0.0, atol=1e-12)
+
+
+def test_lens_figures_of_a_synthetic_focus():
+    """Focus and FWHM of a Gaussian spot, and eta_f of a normally incident
+    plane wave: the disc holds (voxel centres within the radius) x d^2 of
+    flux, counted by brute force."""
+    from oracle import metrics as om
+    nx = ny = 81
+    nz = 5
+    d = 0.1
+    s = 0.6
+    y, x = np.meshgrid((np.arange(ny) - 40) * d, (np.arange(nx) - 40) * d, indexing="ij")
+    plane = np.exp(-(x * x + y * y) / (2 * s * s))
+    E = np.zeros((3, nz, ny, nx), dtype=np.complex128)
+    E[0, 2] = np.sqrt(plane)
+    E[0, 1] = 0.4 * np.sqrt(plane)
+    E[0, 3] = 0.4 * np.sqrt(plane)
+    k = 2 * math.pi / 0.75
+    f = om.lens_figures(E, d, (0, 0, 0), (nx, ny, nz), aperture=1.0, k=k)
+    assert f["focus"] == (40, 40, 2)
+    fw = 2 * math.sqrt(2 * math.log(2)) * s
+    assert f["fwhm"][0] == pytest.approx(fw, rel=5e-3) and f["fwhm"][1] == pytest.approx(fw, rel=5e-3)
+    # a plane wave with a bump to fix the focus: eta_f from the disc count
+    E2 = np.zeros((3, 3, 21, 21), dtype=np.complex128)
+    E2[0] = 1.0
+    f2 = om.lens_figures(E2 + 0.0, 0.1, (0, 0, 0), (21, 21, 3), aperture=1.0, k=k)
+    assert math.isnan(f2["fwhm"][0])                  # a flat field has no width
+    Sz = om.plane_flux(E2[0, 1], E2[1, 1], 0.1, k)
+    assert np.allclose(Sz, 1.0)
+    r = 4.3
+    brute = sum(1 for j in range(21) for i in range(21) if (i - 10) ** 2 + (j - 10) ** 2 <= r * r)
+    yy, xx = np.meshgrid(np.arange(21) - 10, np.arange(21) - 10, indexing="ij")
+    assert float(np.sum(Sz[(xx * xx + yy * yy) <= r * r])) == pytest.approx(brute, rel=1e-12)

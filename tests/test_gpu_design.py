@@ -79,3 +79,29 @@ def test_design_loop_warm_starts_and_improves(device):
     opt.close()
     assert sum(steps[-1].iterations) < sum(steps[0].iterations)
     assert steps[-1].fom > steps[1].fom
+
+
+def test_lens_metrics_match_oracle(device):
+    """Focus, FWHM and focusing efficiency of a solved kinoform field: the
+    library's reductions against the oracle's on the same field."""
+    from oracle import metrics as om
+    d = scenes.lens_design_small()
+    opt = LensOptimizer(d, device, tol=1e-6)
+    eps = torch.full((d.shape[2], d.shape[1], d.shape[0]), 1.0, dtype=torch.float32, device=device)
+    z0, z1 = d.slab
+    with torch.no_grad():
+        eps[z0:z1] = opt.map(opt.p)
+    opt.plan.set_permittivity(eps)
+    E, _ = opt.plan.solve(tol=1e-6, max_iter=20000)
+    nx, ny, nz = d.shape
+    lo, hi = (d.pml[0], d.pml[1], z1), (nx - d.pml[0], ny - d.pml[1], nz - d.pml[2])
+    got = opt.plan.lens_metrics(E, lo, hi, aperture_m=d.D)
+    ref = om.lens_figures(E.cpu().numpy(), d.pitch, lo, hi, aperture=d.D,
+                          k=2 * np.pi * d.n_bg / d.lambda0)
+    opt.close()
+    assert got["focus"] == ref["focus"]
+    assert got["peak"] == pytest.approx(ref["peak"], rel=1e-12)
+    for a in range(3):
+        assert got["fwhm"][a] == pytest.approx(ref["fwhm"][a], rel=1e-9)
+    assert got["eta_f"] == pytest.approx(ref["eta_f"], rel=1e-9)
+    assert 0.0 < got["eta_f"] < 1.0

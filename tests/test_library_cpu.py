@@ -49,12 +49,14 @@ def test_unsupported_lengths(lib):
 
 
 def test_workspace_bytes_cover_fields():
-    # W (24 B/voxel, row pitch padded to 8) + V0 (8 B/voxel) + tables
+    # W (24 B/voxel, row pitch padded to 8) + V0 (8 B/voxel) + tables, partial
+    # sums and the lens-metric scratch (five FP64 complex planes)
     for (nx, ny, nz) in [(64, 64, 64), (275, 275, 315), (621, 621, 261)]:
         b = L.cbs_plan_workspace_bytes(nx, ny, nz)
         nxp = (nx + 7) // 8 * 8
-        assert b >= 24 * nxp * ny * nz + 8 * nx * ny * nz
-        assert b < 24 * nxp * ny * nz + 8 * nx * ny * nz + 4 * 2 ** 20 + 16 * ny * nz
+        assert b >= 24 * nxp * ny * nz + 8 * nx * ny * nz + 5 * 16 * nx * ny
+        assert b < (24 * nxp * ny * nz + 8 * nx * ny * nz + 4 * 2 ** 20 + 16 * ny * nz
+                    + 5 * 16 * nx * ny + 16 * (nx + ny))
 
 
 def _create(nx, ny, nz, pitch=1e-7, lam=1e-6, nbg=1.0, pml=(0, 0, 0), ws=None, wsb=0):
