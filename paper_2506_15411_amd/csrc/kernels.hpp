@@ -531,64 +531,101 @@ kz_pass(CbsArgs a) {
   }
   __syncthreads();
 
-  // level B: thread k1 = t, all three components, Green multiply, inverse B
-  if (t < N1) {
-    float2 v0[N2], v1[N2], v2[N2];
-    float2* L0 = lds;
-    float2* L1 = lds + N * TX;
-    float2* L2 = lds + 2 * N * TX;
-    sfor<0, N2>([&](auto J) {
-      const int o = (N2 * t + CV(J)) * TX + xi;
-      v0[CV(J)] = L0[o];
-      v1[CV(J)] = L1[o];
-      v2[CV(J)] = L2[o];
-    });
-    dft<N2, -1>(v0);
-    dft<N2, -1>(v1);
-    dft<N2, -1>(v2);
-    bool nyx, nyy;
-    const float px = freq_of(x, a.nx, a.pfx, nyx);
-    const float py = freq_of(y, a.ny, a.pfy, nyy);
-    const float ptx = nyx ? 0.f : px, pty = nyy ? 0.f : py;
-    const float pxy2 = px * px + py * py;
-    const float nq_xy = (nyx ? px * px : 0.f) + (nyy ? py * py : 0.f);
-    const float eps = a.eps, e2 = eps * eps;
-    const bool nq_any = nyx || nyy;
-    const float sb = __builtin_amdgcn_rcpf(a.kb2 * a.kb2 + e2);
-    const float2 gb0 = make_float2(-a.kb2 * sb, eps * sb);
-    sfor<0, N2>([&](auto K2) {
-      constexpr int k2 = CV(K2);
-      bool nyz;
-      const float pz = freq_of(t + N1 * k2, a.nz, a.pfz, nyz);
-      const float ptz = nyz ? 0.f : pz;
-      const float p2 = pxy2 + pz * pz;
-      // a = invN / (p2 - kb2 - i eps), b = 1 / (p2 - |pt|^2 - kb2 - i eps)
-      const float r1 = p2 - a.kb2;
-      const float s1 = a.invN * __builtin_amdgcn_rcpf(r1 * r1 + e2);
-      const float2 ga = make_float2(r1 * s1, eps * s1);
-      float2 gb = gb0;   // 1 / (-kb2 - i eps): every mode without a Nyquist component
-      if (nq_any || nyz) {
-        const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
-        const float s2 = __builtin_amdgcn_rcpf(r2 * r2 + e2);
-        gb = make_float2(r2 * s2, eps * s2);
+  // Green's tensor of the column's modes: the x/y parts are fixed per thread
+  float2* L0 = lds;
+  float2* L1 = lds + N * TX;
+  float2* L2 = lds + 2 * N * TX;
+  bool nyx, nyy;
+  const float px = freq_of(x, a.nx, a.pfx, nyx);
+  const float py = freq_of(y, a.ny, a.pfy, nyy);
+  const float ptx = nyx ? 0.f : px, pty = nyy ? 0.f : py;
+  const float pxy2 = px * px + py * py;
+  const float nq_xy = (nyx ? px * px : 0.f) + (nyy ? py * py : 0.f);
+  const float eps = a.eps, e2 = eps * eps;
+  const bool nq_any = nyx || nyy;
+  const float sb = __builtin_amdgcn_rcpf(a.kb2 * a.kb2 + e2);
+  const float2 gb0 = make_float2(-a.kb2 * sb, eps * sb);
+  // v <- G^(p) v / N at z-frequency index kz
+  auto green = [&](float2& u0, float2& u1, float2& u2, int kz) {
+    bool nyz;
+    const float pz = freq_of(kz, a.nz, a.pfz, nyz);
+    const float ptz = nyz ? 0.f : pz;
+    const float p2 = pxy2 + pz * pz;
+    // a = invN / (p2 - kb2 - i eps), b = 1 / (p2 - |pt|^2 - kb2 - i eps)
+    const float r1 = p2 - a.kb2;
+    const float s1 = a.invN * __builtin_amdgcn_rcpf(r1 * r1 + e2);
+    const float2 ga = make_float2(r1 * s1, eps * s1);
+    float2 gb = gb0;   // 1 / (-kb2 - i eps): every mode without a Nyquist component
+    if (nq_any || nyz) {
+      const float r2 = (nq_xy + (nyz ? pz * pz : 0.f)) - a.kb2;
+      const float s2 = __builtin_amdgcn_rcpf(r2 * r2 + e2);
+      gb = make_float2(r2 * s2, eps * s2);
+    }
+    const float2 sp = make_float2(ptx * u0.x + pty * u1.x + ptz * u2.x,
+                                  ptx * u0.y + pty * u1.y + ptz * u2.y);
+    const float2 bs = cmul(gb, sp);
+    u0 = cmul(ga, make_float2(u0.x + ptx * bs.x, u0.y + ptx * bs.y));
+    u1 = cmul(ga, make_float2(u1.x + pty * bs.x, u1.y + pty * bs.y));
+    u2 = cmul(ga, make_float2(u2.x + ptz * bs.x, u2.y + ptz * bs.y));
+  };
+
+  if constexpr (N1 > N2) {
+    // level B: thread k1 = t, all three components, Green multiply, inverse B
+    if (t < N1) {
+      float2 v0[N2], v1[N2], v2[N2];
+      sfor<0, N2>([&](auto J) {
+        const int o = (N2 * t + CV(J)) * TX + xi;
+        v0[CV(J)] = L0[o];
+        v1[CV(J)] = L1[o];
+        v2[CV(J)] = L2[o];
+      });
+      dft<N2, -1>(v0);
+      dft<N2, -1>(v1);
+      dft<N2, -1>(v2);
+      sfor<0, N2>([&](auto K2) {
+        constexpr int k2 = CV(K2);
+        green(v0[k2], v1[k2], v2[k2], t + N1 * k2);
+      });
+      dft<N2, +1>(v0);
+      dft<N2, +1>(v1);
+      dft<N2, +1>(v2);
+      sfor<0, N2>([&](auto J) {
+        const int o = (N2 * t + CV(J)) * TX + xi;
+        L0[o] = v0[CV(J)];
+        L1[o] = v1[CV(J)];
+        L2[o] = v2[CV(J)];
+      });
+    }
+  } else {
+    // N1 <= N2: one thread per k1 would leave most lanes idle and hold 3 N2
+    // values.  Split level B over the 3 N1 threads (component, k1): forward
+    // DFT-N2 per component, the Green multiply spread over the same threads by
+    // frequency, inverse DFT-N2 per component, with the spectra in LDS between.
+    const int cb = t / N1, kb = t - cb * N1;
+    float2* Lb = lds + (cb < 3 ? cb : 0) * N * TX;
+    auto level_b = [&](auto sign) {
+      if (t < 3 * N1) {
+        float2 v[N2];
+        sfor<0, N2>([&](auto J) { v[CV(J)] = Lb[(N2 * kb + CV(J)) * TX + xi]; });
+        dft<N2, decltype(sign)::value>(v);
+        sfor<0, N2>([&](auto J) { Lb[(N2 * kb + CV(J)) * TX + xi] = v[CV(J)]; });
       }
-      const float2 u0 = v0[k2], u1 = v1[k2], u2 = v2[k2];
-      const float2 sp = make_float2(ptx * u0.x + pty * u1.x + ptz * u2.x,
-                                    ptx * u0.y + pty * u1.y + ptz * u2.y);
-      const float2 bs = cmul(gb, sp);
-      v0[k2] = cmul(ga, make_float2(u0.x + ptx * bs.x, u0.y + ptx * bs.y));
-      v1[k2] = cmul(ga, make_float2(u1.x + pty * bs.x, u1.y + pty * bs.y));
-      v2[k2] = cmul(ga, make_float2(u2.x + ptz * bs.x, u2.y + ptz * bs.y));
-    });
-    dft<N2, +1>(v0);
-    dft<N2, +1>(v1);
-    dft<N2, +1>(v2);
-    sfor<0, N2>([&](auto J) {
-      const int o = (N2 * t + CV(J)) * TX + xi;
-      L0[o] = v0[CV(J)];
-      L1[o] = v1[CV(J)];
-      L2[o] = v2[CV(J)];
-    });
+    };
+    level_b(std::integral_constant<int, -1>{});
+    __syncthreads();
+    if (t < 3 * N1) {
+      // thread (part, k1) handles k2 = part, part + 3, ...
+      for (int k2 = cb; k2 < N2; k2 += 3) {
+        const int o = (N2 * kb + k2) * TX + xi;
+        float2 u0 = L0[o], u1 = L1[o], u2 = L2[o];
+        green(u0, u1, u2, kb + N1 * k2);
+        L0[o] = u0;
+        L1[o] = u1;
+        L2[o] = u2;
+      }
+    }
+    __syncthreads();
+    level_b(std::integral_constant<int, +1>{});
   }
   __syncthreads();
 

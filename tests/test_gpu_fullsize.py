@@ -7,6 +7,8 @@ benchmark times (the same plans and kernels; only the inputs differ).
   iterations of the 100 um lens against the FP64 oracle over the whole volume.
 * 275 x 275 x 315 (the 16 um lens): equal-iteration parity with the oracle of
   the forward field, and of the design-slab gradient (forward + adjoint).
+* 189 x 189 x 121 (the 32 um kinoform of the optimisation benchmark):
+  equal-iteration parity of the forward field.
 * The served grids (128^3, 192 x 192 x 256): one Green's-operator application.
 """
 
@@ -142,6 +144,22 @@ def test_lens16_gradient_equal_iterations_vs_oracle(device):
     gref = oc.gradient(g, Eo, ga.E_s, lo, hi, scale=2.0)
     assert grad.shape == gref.shape
     assert np.linalg.norm(grad - gref) / np.linalg.norm(gref) < 1e-3
+
+
+def test_lens32_kinoform_equal_iterations_vs_oracle(device):
+    """The optimisation benchmark volume (189 x 189 x 121 at 177 nm, the 32 um
+    kinoform): equal-iteration parity of the forward field with the oracle."""
+    from oracle import design as od
+    d = scenes.lens32_design()
+    eps = od.eps_of(d.h_init, d).astype(np.float32)
+    p = Plan(d.shape, d.pitch, LAM, d.n_bg, d.pml, device=device)
+    p.set_permittivity(torch.from_numpy(eps).to(device))
+    k = 6
+    E, st = p.solve(tol=0.0, max_iter=k, scattered=True)
+    g = oc.Grid(*d.shape, d.pitch, LAM, d.n_bg, d.pml)
+    res = oc.cbs(g, eps, oc.plane_wave_source(g, eps), tol=0.0, max_iter=k)
+    assert rel_chunked(E, res.E_s) < 1e-4
+    p.close()
 
 
 @pytest.mark.parametrize("shape,pitch", [((128, 128, 128), LAM / 6), ((192, 192, 256), LAM / 12)])

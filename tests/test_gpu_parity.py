@@ -43,7 +43,7 @@ def make(shape, pitch, pml, eps, dev, **kw):
 
 
 SHAPES = [(8, 8, 8), (5, 6, 7), (12, 10, 9), (16, 16, 16), (40, 36, 48), (27, 25, 29),
-          (64, 64, 64), (100, 96, 36)]
+          (64, 64, 64), (100, 96, 36), (20, 18, 121)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
