@@ -177,12 +177,18 @@ constexpr int k1_rows_for(int tm) {
   return best;
 }
 // Columns per z-pass workgroup: a whole brick row (8) unless the exchange
-// buffer of 3 components x 8 columns would leave room for fewer than three
-// workgroups per CU (160 KB of LDS), then half a brick row (measured at
-// 315 = 35 x 9: 0.39 ms with 4 columns against 0.46 ms with 8).
-constexpr int kz_tx_for(int n) {
+// buffer of 3 components x 8 columns (160 KB of LDS per CU) leaves room for
+// fewer than three workgroups and those hold fewer than 12 waves per CU; then
+// half a brick row (measured at 315: split 35 x 9 0.39 ms with 4 columns against
+// 0.46 ms with 8; split 15 x 21, 8 waves per workgroup, 0.27 ms with 8 columns
+// against 0.34 ms with 4).
+constexpr int kz_tx_for(int n1, int n2) {
   if (CBS_KZ_TX > 0) return CBS_KZ_TX;
-  return 3 * n * 8 * 8 + n * 8 <= 53 * 1024 ? 8 : 4;
+  const int n = n1 * n2;
+  const int lds8 = 3 * n * 8 * 8 + n * 8;
+  if (lds8 <= 53 * 1024) return 8;
+  const int waves8 = round64(8 * cmax(3 * n2, n1)) / 64;
+  return waves8 * ((160 * 1024) / lds8) >= 12 ? 8 : 4;
 }
 
 template <int N1, int N2>
@@ -685,7 +691,7 @@ void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
 
 template <int N1, int N2>
 void launch_kz(const CbsArgs& a, hipStream_t s) {
-  constexpr int TX = kz_tx_for(N1 * N2);
+  constexpr int TX = kz_tx_for(N1, N2);
   using G = ZGeom<N1, N2, TX>;
   dim3 grid((unsigned)((long long)(a.nxp / TX) * a.ny));
   hipLaunchKernelGGL((kz_pass<N1, N2, TX>), grid, dim3(G::THREADS), 0, s, a);
