@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import re
 import json
+import math
 import os
 import sys
 import time
@@ -166,8 +167,11 @@ def design_bench(args, dev):
         opt.plan.set_permittivity(opt.eps)
         E, _ = opt.plan.solve(tol=args.tol, max_iter=args.max_iter, check_every=args.check_every)
         f = opt.plan.lens_metrics(E, *search, aperture_m=d.D)
-        return {"eta_f": round(f["eta_f"], 4), "fwhm_um": [round(w * 1e6, 3) for w in f["fwhm"]],
-                "focus": list(f["focus"]), "peak": round(f["peak"], 3)}
+
+        def num(v, scale=1.0, nd=4):   # NaN (no half-maximum crossing) -> null
+            return round(v * scale, nd) if math.isfinite(v) else None
+        return {"eta_f": num(f["eta_f"]), "fwhm_um": [num(w, 1e6, 3) for w in f["fwhm"]],
+                "focus": list(f["focus"]), "peak": num(f["peak"], 1.0, 3)}
 
     start = figures()
     log(f"[bench] design start: {start}")

@@ -92,11 +92,16 @@ class LensOptimizer:
     def __init__(self, d: LensDesign, device=None, smoothing: bool = True, tol: float = 1e-4,
                  max_iter: int = 20000, lr: float = 0.3, betas=(0.9, 0.999), adam_eps: float = 1e-6,
                  check_every: int = 20):
+        nx, ny, nz = d.shape
+        z0, z1 = d.slab
+        if z0 < d.pml[2] or z1 > nz - d.pml[2]:
+            raise ValueError(f"lens slab z [{z0}, {z1}) reaches into the absorbing layer")
+        if not all(d.pml[a] <= d.r0[a] < d.shape[a] - d.pml[a] for a in range(3)):
+            raise ValueError(f"focus {d.r0} lies in the absorbing layer")
         self.d = d
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         self.map = DesignMap(d, self.device, smoothing)
         self.plan = Plan(d.shape, d.pitch, d.lambda0, d.n_bg, d.pml, device=self.device)
-        nx, ny, nz = d.shape
         self.p = torch.tensor(d.h_init, dtype=torch.float32, device=self.device, requires_grad=True)
         self.opt = torch.optim.Adam([self.p], lr=lr, betas=betas, eps=adam_eps, maximize=True)
         self.eps = torch.full((nz, ny, nx), d.n_bg ** 2, dtype=torch.float32, device=self.device)
