@@ -195,6 +195,92 @@ CBS_HD void dft_prime(float2 (&a)[P]) {
   a[0] = tot;
 }
 
+constexpr long long ct_powmod(long long b, long long e, long long m) {
+  long long r = 1;
+  b %= m;
+  while (e > 0) {
+    if (e & 1) r = r * b % m;
+    b = b * b % m;
+    e >>= 1;
+  }
+  return r;
+}
+// smallest primitive root of the prime p: g^((p-1)/q) != 1 for every prime q | p-1
+constexpr int ct_primitive_root(int p) {
+  for (int g = 2; g < p; ++g) {
+    bool ok = true;
+    for (int q = 2; q < p; ++q)
+      if ((p - 1) % q == 0 && ct_is_prime(q) && ct_powmod(g, (p - 1) / q, p) == 1) ok = false;
+    if (ok) return g;
+  }
+  return 1;
+}
+
+// Odd prime P with H = (P-1)/2 = 2M, M >= 4: the conjugate-pair form with its
+// two H x H products taken in Rader order.  With g a primitive root, e_r =
+// g^r mod P and f_q = g^-q mod P (r, q < H), and u_r = a[e_r] + a[P-e_r],
+// v_r = a[e_r] - a[P-e_r]:
+//   X[f_q]     = a0 + sum_r c_{r-q} u_r + i S sum_r s_{r-q} v_r,
+//   X[P - f_q] = a0 + sum_r c_{r-q} u_r - i S sum_r s_{r-q} v_r,
+// c_m = cos(2 pi g^m / P), s_m = sin(2 pi g^m / P); since g^H = -1, c has
+// period H and s changes sign after H.  Split r = r0 + M r1, q = q0 + M q1:
+// the cosine matrix is [[A, B], [B, A]], so it acts on u0 +- u1 through
+// (A +- B)/2 (two M x M products instead of four); the sine matrix is
+// [[A', B'], [-B', A']], taken as A'(v0 + v1) + (B' - A') v1 and
+// A'(v0 + v1) - (A' + B') v0 (three instead of four).
+template <int P, int S>
+CBS_HD void dft_prime_split(float2 (&a)[P]) {
+  constexpr int H = (P - 1) / 2;
+  constexpr int M = H / 2;
+  constexpr long long g = ct_primitive_root(P);
+  constexpr long long ginv = ct_powmod(g, P - 2, P);
+  float2 pu[M], mu[M], v0[M], v1[M], vs[M];
+  sfor<0, M>([&](auto R0) {
+    constexpr int r0 = CV(R0);
+    constexpr int e0 = (int)ct_powmod(g, r0, P), e1 = (int)ct_powmod(g, r0 + M, P);
+    const float2 u0 = cadd(a[e0], a[P - e0]), u1 = cadd(a[e1], a[P - e1]);
+    v0[r0] = csub(a[e0], a[P - e0]);
+    v1[r0] = csub(a[e1], a[P - e1]);
+    pu[r0] = cadd(u0, u1);
+    mu[r0] = csub(u0, u1);
+    vs[r0] = cadd(v0[r0], v1[r0]);
+  });
+  const float2 x0 = a[0];
+  float2 tot = x0;
+  sfor<0, M>([&](auto R0) { tot = cadd(tot, pu[CV(R0)]); });
+  sfor<0, M>([&](auto Q0) {
+    constexpr int q0 = CV(Q0);
+    float2 cp = x0, cm = make_float2(0.f, 0.f);
+    float2 k1 = make_float2(0.f, 0.f), k2 = k1, k3 = k1;
+    sfor<0, M>([&](auto R0) {
+      constexpr int r0 = CV(R0);
+      constexpr int d = ((r0 - q0) % (2 * H) + 2 * H) % (2 * H);
+      constexpr CS w0 = ct_cis(ct_powmod(g, d, P), P);
+      constexpr CS w1 = ct_cis(ct_powmod(g, d + M, P), P);
+      constexpr float kp = float(0.5 * (w0.c + w1.c)), km = float(0.5 * (w0.c - w1.c));
+      constexpr float al = float(w0.s), bm = float(w1.s - w0.s), ap = float(w0.s + w1.s);
+      cp.x += kp * pu[r0].x;
+      cp.y += kp * pu[r0].y;
+      cm.x += km * mu[r0].x;
+      cm.y += km * mu[r0].y;
+      k1.x += al * vs[r0].x;
+      k1.y += al * vs[r0].y;
+      k2.x += bm * v1[r0].x;
+      k2.y += bm * v1[r0].y;
+      k3.x += ap * v0[r0].x;
+      k3.y += ap * v0[r0].y;
+    });
+    const float2 At = cadd(cp, cm), Ab = csub(cp, cm);   // q = q0 and q = q0 + M
+    const float2 Bt = cadd(k1, k2), Bb = csub(k1, k3);
+    constexpr int ft = (int)ct_powmod(ginv, q0, P), fb = (int)ct_powmod(ginv, q0 + M, P);
+    a[ft] = make_float2(At.x - float(S) * Bt.y, At.y + float(S) * Bt.x);
+    a[P - ft] = make_float2(At.x + float(S) * Bt.y, At.y - float(S) * Bt.x);
+    a[fb] = make_float2(Ab.x - float(S) * Bb.y, Ab.y + float(S) * Bb.x);
+    a[P - fb] = make_float2(Ab.x + float(S) * Bb.y, Ab.y - float(S) * Bb.x);
+  });
+  a[0] = tot;
+}
+
 template <int N, int S>
 CBS_HD void dft(float2 (&a)[N]) {
   static_assert(S == 1 || S == -1, "sign");
@@ -207,6 +293,8 @@ CBS_HD void dft(float2 (&a)[N]) {
     dft3<S>(a[0], a[1], a[2]);
   } else if constexpr (N == 4) {
     dft4<S>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (ct_is_prime(N) && (N - 1) % 4 == 0 && N >= 17) {
+    dft_prime_split<N, S>(a);
   } else if constexpr (ct_is_prime(N)) {
     dft_prime<N, S>(a);
   } else {
