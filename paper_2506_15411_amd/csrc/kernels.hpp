@@ -56,6 +56,12 @@ constexpr int kBrick = 8;
 #ifndef CBS_K1_PREFETCH
 #define CBS_K1_PREFETCH 2    // x-pass: 1 = load V0, 2 = load V0 and E_s before the inverse FFT
 #endif
+#ifndef CBS_K1_PF_E
+#define CBS_K1_PF_E 1024     // x-pass: how many of a thread's E_s elements the early load covers
+#endif
+#ifndef CBS_K1_PF_V
+#define CBS_K1_PF_V 1024     // x-pass: how many of a thread's V0 elements the early load covers
+#endif
 #ifndef CBS_Y_TW_GLOBAL
 #define CBS_Y_TW_GLOBAL 0    // y pass: read twiddles from global memory (frees LDS for a 4th block)
 #endif
@@ -64,6 +70,14 @@ constexpr int kBrick = 8;
 #endif
 #ifndef CBS_KZ_TX
 #define CBS_KZ_TX 0          // z-pass: columns per workgroup, 8 or 4 (0: per-size rule)
+#endif
+#ifndef CBS_TW_STAGED
+#define CBS_TW_STAGED 1      // y and z passes: load the twiddle table alongside the first
+                             // data loads (0: fill it first, one dependent load per entry)
+#endif
+#ifndef CBS_K1_TW
+#define CBS_K1_TW 2          // x-pass twiddle table: 0 = fill loop, 1 = all entries loaded at
+                             // once and written before the operand loads, 2 = staged as above
 #endif
 #ifndef CBS_LAG_RESIDUAL
 #define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
@@ -231,6 +245,32 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned total) {
   return k * q + (k < r ? k : r) + j;
 }
 
+// A pass's inter-level twiddle table is copied to LDS by every workgroup.
+// Staged: issue() starts all of this thread's table loads at once, the caller
+// then issues its first data loads, and commit() writes the table to LDS
+// before the barrier, so the table's latency overlaps the data loads instead
+// of preceding them.
+template <int N, int THREADS>
+struct TwStage {
+  static constexpr int K = (N + THREADS - 1) / THREADS;
+  float2 v[K];
+  // rounds that lie wholly inside the table need no bounds test
+  template <int I>
+  static constexpr bool kFull = (I + 1) * THREADS <= N;
+  __device__ __forceinline__ void issue(const float2* g, int tid) {
+    sfor<0, K>([&](auto I) {
+      const int i = tid + CV(I) * THREADS;
+      if (kFull<CV(I)> || i < N) v[CV(I)] = g[i];
+    });
+  }
+  __device__ __forceinline__ void commit(float2* s, int tid) const {
+    sfor<0, K>([&](auto I) {
+      const int i = tid + CV(I) * THREADS;
+      if (kFull<CV(I)> || i < N) s[i] = v[CV(I)];
+    });
+  }
+};
+
 // ---------------------------------------------------------------------------
 // block reduction of two doubles (residual partials)
 // ---------------------------------------------------------------------------
@@ -278,7 +318,13 @@ k1_xpass(CbsArgs a) {
 
   const int tid = threadIdx.x;
   __shared__ float2 tw[N];
-  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
+  TwStage<N, G::THREADS> tws;
+  if constexpr (CBS_K1_TW == 0) {
+    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
+  } else {
+    tws.issue(a.twx, tid);
+    if constexpr (CBS_K1_TW == 1) tws.commit(tw, tid);
+  }
 
   // block -> (component, row group, z); the three components of the same rows
   // are adjacent in the remapped order so V0 is shared in one L2
@@ -306,26 +352,35 @@ k1_xpass(CbsArgs a) {
   // inverse transform)
   constexpr bool PF_V = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 1;
   constexpr bool PF_E = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 2;
-  float2 pv[PF_V ? N2 : 1], pe[PF_E ? N2 : 1];
+  constexpr int kPfE = PF_E ? (CBS_K1_PF_E < N2 ? CBS_K1_PF_E : N2) : 0;
+  constexpr int kPfV = PF_V ? (CBS_K1_PF_V < N2 ? CBS_K1_PF_V : N2) : 0;
+  float2 pv[kPfV > 0 ? kPfV : 1], pe[kPfE > 0 ? kPfE : 1];
   const float2* v0t = a.V0 + vbase + t;   // this thread's elements are t + N1 m
   float2* et = a.E + ebase + t;
   if constexpr (PF_V) {
-    if (ok && t < N1) sfor<0, N2>([&](auto M) { pv[CV(M)] = v0t[N1 * CV(M)]; });
+    if (ok && t < N1) sfor<0, kPfV>([&](auto M) { pv[CV(M)] = v0t[N1 * CV(M)]; });
   }
   if constexpr (PF_E) {
-    if (ok && t < N1) sfor<0, N2>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
+    if (ok && t < N1) sfor<0, kPfE>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
   }
-
-  __syncthreads();   // the twiddle table is in LDS
 
   // element x of this thread's row in the bricks
   float2* wrow = wb + line * kBrick;
   auto wat = [&](int x) -> float2& { return wrow[(x >> 3) * bstride + (x & 7)]; };
+  // inverse level A input: thread j2 = t < N2 holds row[j2 + N2 j1]
+  float2 b[N1];
+  auto load_a = [&]() {
+    if (ok && t < N2) sfor<0, N1>([&](auto J1) { b[CV(J1)] = wat(t + N2 * CV(J1)); });
+  };
+  constexpr bool kStaged = CBS_K1_TW == 2;
+  if constexpr (MODE != K1_FWD && kStaged) load_a();
+  if constexpr (kStaged) tws.commit(tw, tid);
+  __syncthreads();   // the twiddle table is in LDS
+
   if constexpr (MODE != K1_FWD) {
-    // inverse level A: thread j2 = t < N2, DFT-N1 over row[j2 + N2 j1]
+    if constexpr (!kStaged) load_a();
+    // inverse level A: DFT-N1 over row[j2 + N2 j1]
     if (ok && t < N2) {
-      float2 b[N1];
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = wat(t + N2 * CV(J1)); });
       dft<N1, +1>(b);
       const float2* twt = tw + t * N1;   // exp(-2 pi i t k1 / N), conjugated below
       sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmulc(b[CV(K1)], twt[CV(K1)]); });
@@ -358,9 +413,9 @@ k1_xpass(CbsArgs a) {
       const int x = t + N1 * CV(M);
       float2 e;
       float2 v0;
-      if constexpr (PF_V) v0 = pv[CV(M)]; else v0 = v0t[N1 * CV(M)];
+      if constexpr (CV(M) < kPfV) v0 = pv[CV(M)]; else v0 = v0t[N1 * CV(M)];
       if constexpr (MODE == K1_ITER) {
-        if constexpr (PF_E) e = pe[CV(M)]; else e = et[N1 * CV(M)];
+        if constexpr (CV(M) < kPfE) e = pe[CV(M)]; else e = et[N1 * CV(M)];
         // gamma = 1 + i V0 / eps
         const float2 gm = make_float2(1.0f - v0.y * a.inv_eps, v0.x * a.inv_eps);
         const float2 d = cmul(gm, csub(v[CV(M)], e));
@@ -442,7 +497,12 @@ ky_pass(CbsArgs a) {
     __syncthreads();
   }
 #if !CBS_Y_TW_GLOBAL
-  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
+  TwStage<N, G::THREADS> tws;
+  if constexpr (CBS_TW_STAGED) {
+    tws.issue(a.twy, tid);
+  } else {
+    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
+  }
 #endif
   const int xi = tid % TX;
   const int t = tid / TX;
@@ -457,17 +517,26 @@ ky_pass(CbsArgs a) {
   // the tile is brick (c, z, bx): ny rows of 8 columns, contiguous
   float2* col = a.W + c * a.sW + ((long long)z * a.gx + bx) * a.ny * kBrick + xi;
   const long long ps = kBrick;
-  __syncthreads();
-  if (t < N2) {
-    float2 b[N1];
-    if (xok) {
-      // per-thread base once; each load then adds a uniform stride
-      const float2* ct = col + (long long)t * ps;
-      const long long st = (long long)N2 * ps;
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = ct[CV(J1) * st]; });
-    } else {
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+  float2 b[N1];
+  auto load_a = [&]() {
+    if (t < N2) {
+      if (xok) {
+        // per-thread base once; each load then adds a uniform stride
+        const float2* ct = col + (long long)t * ps;
+        const long long st = (long long)N2 * ps;
+        sfor<0, N1>([&](auto J1) { b[CV(J1)] = ct[CV(J1) * st]; });
+      } else {
+        sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+      }
     }
+  };
+  if constexpr (CBS_TW_STAGED) load_a();
+#if !CBS_Y_TW_GLOBAL
+  if constexpr (CBS_TW_STAGED) tws.commit(tw, tid);
+#endif
+  __syncthreads();
+  if constexpr (!CBS_TW_STAGED) load_a();
+  if (t < N2) {
     dft<N1, S>(b);
     const float2* twt = tw + t * N1;
     sfor<0, N1>([&](auto K1) {
@@ -499,7 +568,12 @@ kz_pass(CbsArgs a) {
   __shared__ float2 tw[N];
   if (a.st->done) return;
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
+  TwStage<N, G::THREADS> tws;
+  if constexpr (CBS_TW_STAGED) {
+    tws.issue(a.twz, tid);
+  } else {
+    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
+  }
   const int xi = tid % TX;
   const int t = tid / TX;
   // remapped order: the kBrick / TX parts of one brick row, then y, then the
@@ -515,20 +589,29 @@ kz_pass(CbsArgs a) {
   const bool xok = x < a.nx;
   const long long plane = (long long)a.ny * a.nxp;   // z stride (gx bricks of ny x 8)
   float2* colbase = a.W + ((long long)brick * a.ny + y) * kBrick + part * TX + xi;
-  __syncthreads();
 
   const long long zst = (long long)N2 * plane;  // z stride between the samples of one DFT-N1
   // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
   const int ca = t / N2;
   const int j2 = t - ca * N2;
-  if (t < 3 * N2) {
-    const float2* col = colbase + ca * a.sW + (long long)j2 * plane;
-    float2 b[N1];
-    if (xok) {
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[CV(J1) * zst]; });
-    } else {
-      sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+  float2 b[N1];
+  auto load_a = [&]() {
+    if (t < 3 * N2) {
+      const float2* col = colbase + ca * a.sW + (long long)j2 * plane;
+      if (xok) {
+        sfor<0, N1>([&](auto J1) { b[CV(J1)] = col[CV(J1) * zst]; });
+      } else {
+        sfor<0, N1>([&](auto J1) { b[CV(J1)] = make_float2(0.f, 0.f); });
+      }
     }
+  };
+  if constexpr (CBS_TW_STAGED) {
+    load_a();
+    tws.commit(tw, tid);
+  }
+  __syncthreads();
+  if constexpr (!CBS_TW_STAGED) load_a();
+  if (t < 3 * N2) {
     dft<N1, -1>(b);
     const float2* twt = tw + j2 * N1;
     sfor<0, N1>([&](auto K1) { b[CV(K1)] = cmul(b[CV(K1)], twt[CV(K1)]); });
