@@ -10,6 +10,11 @@ by its own device-side stopping rule, independent of quanta, and every
 reduction is fixed-order, so a request's result is bit-identical alone and in
 the mix.  All arithmetic runs in libcbs; this module only schedules.
 
+A request the library rejects (an invalid medium: gain, a non-finite value,
+material in the absorbing layer) or whose solve diverges (non-finite residual)
+fails alone: its result carries the library's negative status, no fields or
+gradient, and the other requests are served as if it had not been there.
+
 Latency is arrival -> result complete in device memory.
 """
 
@@ -168,7 +173,13 @@ class Server:
     def _next_phase(self, job: _Job) -> bool:
         """Called when the current solve stopped; True when the job is complete."""
         s = job.slot
-        st = s.plan.end()
+        try:
+            st = s.plan.end()
+        except L.CbsError as e:
+            if e.code != L.CBS_E_DIVERGED:
+                raise
+            job.status = e.code       # the plan has left the solve and is reusable
+            return True
         job.iters[job.phase] = st.iterations
         if st.status not in (L.CBS_OK,):
             job.status = st.status
@@ -185,14 +196,15 @@ class Server:
         s = job.slot
         sc = job.req.scene
         grad = None
-        if job.req.kind == "adjoint":
+        failed = job.status < 0
+        if job.req.kind == "adjoint" and not failed:
             lo, hi = sc.design_box
             grad = s.plan.gradient(s.E, s.Ea, lo, hi, scale=2.0)
         s.stream.synchronize()
         fin = time.perf_counter() - t0
         res = ServedResult(job.req.rid, job.req.kind, tuple(sc.shape), job.status,
                            tuple(job.iters), job.req.arrival, job.admitted, fin)
-        if keep:
+        if keep and not failed:
             with torch.cuda.stream(s.stream):   # ordered before the slot's next use
                 res.E = s.E.clone()
                 if job.req.kind == "adjoint":
@@ -222,7 +234,17 @@ class Server:
                     self.refused += 1
                     break
                 job = _Job(waiting.popleft(), slot, time.perf_counter() - t0)
-                self._start(job)
+                try:
+                    self._start(job)
+                except L.CbsError as e:
+                    if e.code != L.CBS_E_INVALID:
+                        raise
+                    job.status = e.code
+                    results.append(self._finish(job, t0, keep_fields))
+                    if progress is not None:
+                        progress(results[-1], len(results))
+                    self._release(slot, time.perf_counter() - t0)
+                    continue
                 active.append(job)
             if not active:
                 if pending:
@@ -263,22 +285,28 @@ class Server:
             p = slot.plan
             with torch.cuda.stream(slot.stream):
                 slot.eps.copy_(torch.from_numpy(r.scene.eps_r))
-            p.set_permittivity(slot.eps)
-            _, s1 = p.solve(slot.E, tol=self.tol, max_iter=self.max_iter, check_every=20)
-            its = (s1.iterations, 0)
+            its = (0, 0)
             grad = None
-            status = s1.status
-            if r.kind == "adjoint":
-                _, s2 = p.adjoint(E_fwd=slot.E, r0=r.scene.r0, E_adj=slot.Ea, tol=self.tol,
-                                  max_iter=self.max_iter, check_every=20)
-                lo, hi = r.scene.design_box
-                grad = p.gradient(slot.E, slot.Ea, lo, hi, scale=2.0)
-                its = (s1.iterations, s2.iterations)
-                status = status or s2.status
+            try:
+                p.set_permittivity(slot.eps)
+                _, s1 = p.solve(slot.E, tol=self.tol, max_iter=self.max_iter, check_every=20)
+                its = (s1.iterations, 0)
+                status = s1.status
+                if r.kind == "adjoint":
+                    _, s2 = p.adjoint(E_fwd=slot.E, r0=r.scene.r0, E_adj=slot.Ea, tol=self.tol,
+                                      max_iter=self.max_iter, check_every=20)
+                    lo, hi = r.scene.design_box
+                    grad = p.gradient(slot.E, slot.Ea, lo, hi, scale=2.0)
+                    its = (s1.iterations, s2.iterations)
+                    status = status or s2.status
+            except L.CbsError as e:
+                if e.code not in (L.CBS_E_INVALID, L.CBS_E_DIVERGED):
+                    raise
+                status = e.code
             slot.stream.synchronize()
             fin = time.perf_counter() - t0
             res = ServedResult(r.rid, r.kind, tuple(r.scene.shape), status, its, r.arrival, adm, fin)
-            if keep_fields:
+            if keep_fields and status >= 0:
                 with torch.cuda.stream(slot.stream):
                     res.E = slot.E.clone()
                     if r.kind == "adjoint":

@@ -185,6 +185,24 @@ def test_warm_start_continues_the_iteration(device):
     assert rel(E.cpu().numpy(), Eo) < 1e-4
 
 
+def test_non_finite_warm_start_reports_divergence(device):
+    """A warm start from a field holding a NaN makes the residual non-finite:
+    the solve stops at its first check with CBS_E_DIVERGED instead of running
+    to max_iter, and the plan stays usable (a cold solve afterwards matches
+    the oracle)."""
+    shape, pml = (12, 10, 14), (2, 2, 3)
+    eps = scenes.random_passive_eps(shape, pml, 41)
+    g, p = make(shape, LAM / 8, pml, eps, device)
+    E, _ = p.solve(tol=0.0, max_iter=15)
+    E[1, 5, 4, 3] = complex(float("nan"), 0.0)
+    with pytest.raises(L.CbsError) as ei:
+        p.solve(E, tol=1e-6, max_iter=500, check_every=10, warm=True)
+    assert ei.value.code == L.CBS_E_DIVERGED and "non-finite" in str(ei.value)
+    E2, st = p.solve(tol=0.0, max_iter=15)
+    Eo, _ = oc.solve_forward(g, eps, tol=0.0, max_iter=15)
+    assert st.iterations == 15 and rel(E2.cpu().numpy(), Eo) < 1e-4
+
+
 def test_repeat_is_bitwise_identical(device):
     sc = scenes.sphere_scene(32, LAM / 6, 0.8e-6, 1.45, 1.0, (4, 4, 6), supersample=4)
     _, p = make(sc.shape, sc.pitch, sc.pml, sc.eps_r, device)

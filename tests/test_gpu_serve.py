@@ -7,6 +7,7 @@ import pytest
 import torch
 
 from oracle import cbs as oc
+from paper_2506_15411_amd import libcbs as L
 from paper_2506_15411_amd import scenes
 from paper_2506_15411_amd.serve import Server, slot_bytes, summarize
 
@@ -69,4 +70,28 @@ def test_admission_waits_for_memory(device):
     assert len(res) == len(tr) and all(r.status == 0 for r in res)
     assert srv.used <= srv.budget
     assert srv.refused > 0          # some admissions had to wait for memory
+    srv.close()
+
+
+def test_a_rejected_request_fails_alone(device):
+    """A request with material inside the absorbing layer is rejected by the
+    library: in the batched run and in the one-at-a-time run its result
+    carries CBS_E_INVALID and nothing else, while every other request
+    completes exactly as it does without the bad one in the trace."""
+    import dataclasses
+    tr = small_trace(6, seed=7)
+    bad_scene = dataclasses.replace(tr[2].scene, eps_r=tr[2].scene.eps_r.copy())
+    nx, ny, nz = bad_scene.shape
+    bad_scene.eps_r[0, ny // 2, nx // 2] = 2.25
+    bad = scenes.ServedRequest(99, "adjoint", bad_scene, tr[2].arrival)
+    srv = Server(device, max_active=3, tol=1e-5)
+    ref = {r.rid: r for r in srv.run(tr, keep_fields=True, realtime=False)}
+    for run in (lambda t: srv.run(t, keep_fields=True, realtime=False),
+                lambda t: srv.run_sequential(t, keep_fields=True)):
+        got = {r.rid: r for r in run(tr[:2] + [bad] + tr[2:])}
+        assert got[99].status == L.CBS_E_INVALID and got[99].E is None and got[99].grad is None
+        for rid, r in ref.items():
+            assert got[rid].status == r.status and got[rid].iterations == r.iterations
+            assert torch.equal(got[rid].E, r.E)
+        assert summarize(list(got.values()))["not_ok"] == 1
     srv.close()
