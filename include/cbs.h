@@ -132,7 +132,9 @@ int cbs_plan_set_shift_factor(cbs_plan_t plan, double kappa);
  * (CBS_C64).  Validates finiteness, Im eps_r >= 0 and eps_r == n_bg^2 (at
  * float32) inside the absorbing layer, builds the potential on the device and
  * computes eps = kappa max|K - kb^2| with the maximum taken in FP64 (floor
- * 1e-3 kb^2 on the maximum).  Synchronises the stream. */
+ * 1e-3 kb^2 on the maximum).  Returns CBS_E_INVALID for a medium that fails
+ * these checks or whose eps d^2 reaches 1e30 (the FP32 iteration would
+ * overflow).  Synchronises the stream. */
 int cbs_set_permittivity(cbs_plan_t plan, const void* eps_r_dev, int dtype);
 
 /* Forward solve.  src = NULL means an x-polarised plane wave.  E_dev is

@@ -971,6 +971,9 @@ int cbs_set_permittivity(cbs_plan_t p, const void* eps_r, int dtype) {
   if (fl & 4u) return fail(CBS_E_INVALID, "eps_r must equal n_bg^2 inside the absorbing layer");
   const double floor_ = 1e-3 * p->kb * p->kb * d2;
   const double eps_d2 = p->shift_factor * (mx > floor_ ? mx : floor_);
+  // the iteration forms (V0 - i eps) E in FP32: keep the shift far inside its range
+  if (!(eps_d2 < 1e30))
+    return fail(CBS_E_INVALID, "eps_r contrast too large for the FP32 iteration (shift %g)", eps_d2);
   p->eps = eps_d2 / d2;
   p->have_eps = true;
   return CBS_OK;

@@ -219,7 +219,7 @@ def test_repeat_is_bitwise_identical(device):
 
 
 @pytest.mark.parametrize("bad,frag", [("gain", "gain"), ("layer", "absorbing layer"),
-                                      ("nan", "non-finite")])
+                                      ("nan", "non-finite"), ("huge", "FP32")])
 def test_invalid_media_are_rejected(bad, frag, device):
     shape, pml = (8, 8, 8), (2, 2, 2)
     eps = scenes.random_passive_eps(shape, pml, 1, loss=0.1)
@@ -227,6 +227,8 @@ def test_invalid_media_are_rejected(bad, frag, device):
         eps[4, 4, 4] = 1.5 - 0.1j
     elif bad == "layer":
         eps[0, 4, 4] = 1.2
+    elif bad == "huge":
+        eps[3, 3, 3] = 1e35
     else:
         eps[3, 3, 3] = np.nan
     p = Plan(shape, LAM / 8, LAM, 1.0, pml, device=device)
