@@ -79,6 +79,10 @@ constexpr int kBrick = 8;
 #define CBS_K1_TW 2          // x-pass twiddle table: 0 = fill loop, 1 = all entries loaded at
                              // once and written before the operand loads, 2 = staged as above
 #endif
+#ifndef CBS_LOAD_PRIO
+#define CBS_LOAD_PRIO 2      // x-pass wave priority while a work-group issues its first loads,
+                             // used where the iteration kernel holds at most two waves per SIMD
+#endif
 #ifndef CBS_LAG_RESIDUAL
 #define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
                              // residual reduction (no separate launch per iteration)
@@ -158,6 +162,7 @@ struct CbsArgs {
   float2* fout;                 // Green output
   double* partials;             // 2 doubles per K1 block
   int k1_blocks;                // number of K1 blocks (partials to reduce)
+  int k1_prio;                  // x-pass: raise wave priority for the load phase (set by launch_k1)
   double* hist;                 // residual history
   DevState* st;
   int src;                      // SrcKind
@@ -317,6 +322,9 @@ k1_xpass(CbsArgs a) {
   if (MODE == K1_ITER && a.st->done) return;
 
   const int tid = threadIdx.x;
+  // with few waves per SIMD, a work-group's load phase would otherwise wait
+  // behind the other waves' vector work
+  if (CBS_LOAD_PRIO > 0 && a.k1_prio) __builtin_amdgcn_s_setprio(CBS_LOAD_PRIO);
   __shared__ float2 tw[N];
   TwStage<N, G::THREADS> tws;
   if constexpr (CBS_K1_TW == 0) {
@@ -376,6 +384,7 @@ k1_xpass(CbsArgs a) {
   if constexpr (MODE != K1_FWD && kStaged) load_a();
   if constexpr (kStaged) tws.commit(tw, tid);
   __syncthreads();   // the twiddle table is in LDS
+  if (CBS_LOAD_PRIO > 0 && a.k1_prio) __builtin_amdgcn_s_setprio(0);
 
   if constexpr (MODE != K1_FWD) {
     if constexpr (!kStaged) load_a();
@@ -750,9 +759,30 @@ struct SizeOps {
 
 constexpr int kTY = kBrick;   // columns per y-pass block
 
+// Whether the iteration kernel holds at most two waves per SIMD (occupancy
+// API, once per size): then its work-groups raise their priority for the load
+// phase (measured at 621 = 27 x 23, two waves: x-pass 2.36 -> 2.30 ms; at
+// 275 = 25 x 11, three waves: 0.58 -> 0.60 ms, so not there).
 template <int N1, int N2>
-void launch_k1(const CbsArgs& a, int mode, hipStream_t s) {
+int k1_low_occupancy() {
+  static int v = -1;
+  if (v < 0) {
+    using G = XGeom<N1, N2>;
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k1_xpass<N1, N2, K1_ITER>, G::THREADS,
+                                                     0) != hipSuccess || b <= 0)
+      v = 0;
+    else
+      v = b * (G::THREADS / 64) <= 2 * 4 ? 1 : 0;   // 4 SIMDs per CU
+  }
+  return v;
+}
+
+template <int N1, int N2>
+void launch_k1(const CbsArgs& a_in, int mode, hipStream_t s) {
   using G = XGeom<N1, N2>;
+  CbsArgs a = a_in;
+  a.k1_prio = k1_low_occupancy<N1, N2>();
   const unsigned nb = 3u * (unsigned)a.gy * (unsigned)a.nz;
   if (mode == K1_FWD)
     hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD>), dim3(nb), dim3(G::THREADS), 0, s, a);
