@@ -83,6 +83,10 @@ constexpr int kBrick = 8;
 #define CBS_LOAD_PRIO 2      // x-pass wave priority while a work-group issues its first loads,
                              // used where the iteration kernel holds at most two waves per SIMD
 #endif
+#ifndef CBS_Y_PRIO
+#define CBS_Y_PRIO 2         // y pass: the same load-phase priority where it holds at most
+                             // three waves per SIMD (0: never)
+#endif
 #ifndef CBS_LAG_RESIDUAL
 #define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
                              // residual reduction (no separate launch per iteration)
@@ -163,6 +167,7 @@ struct CbsArgs {
   double* partials;             // 2 doubles per K1 block
   int k1_blocks;                // number of K1 blocks (partials to reduce)
   int k1_prio;                  // x-pass: raise wave priority for the load phase (set by launch_k1)
+  int ky_prio;                  // y pass: the same (set by launch_ky)
   double* hist;                 // residual history
   DevState* st;
   int src;                      // SrcKind
@@ -491,6 +496,7 @@ ky_pass(CbsArgs a) {
 #endif
   if (a.st->done) return;
   const int tid = threadIdx.x;
+  if (CBS_Y_PRIO > 0 && a.ky_prio) __builtin_amdgcn_s_setprio(CBS_Y_PRIO);
   if (CBS_LAG_RESIDUAL && S < 0 && blockIdx.x == 0 && a.st->pending) {
     // finish the previous iteration's residual (stream order: the x pass that
     // wrote the partials has completed); lds is still unused here
@@ -544,6 +550,7 @@ ky_pass(CbsArgs a) {
   if constexpr (CBS_TW_STAGED) tws.commit(tw, tid);
 #endif
   __syncthreads();
+  if (CBS_Y_PRIO > 0 && a.ky_prio) __builtin_amdgcn_s_setprio(0);
   if constexpr (!CBS_TW_STAGED) load_a();
   if (t < N2) {
     dft<N1, S>(b);
@@ -793,8 +800,25 @@ void launch_k1(const CbsArgs& a_in, int mode, hipStream_t s) {
 }
 
 template <int N1, int N2>
-void launch_ky(const CbsArgs& a, int sign, hipStream_t s) {
+int ky_low_occupancy() {
+  static int v = -1;
+  if (v < 0) {
+    using G = YGeom<N1, N2, kTY>;
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, ky_pass<N1, N2, kTY, -1>, G::THREADS,
+                                                     0) != hipSuccess || b <= 0)
+      v = 0;
+    else
+      v = b * (G::THREADS / 64) <= 3 * 4 ? 1 : 0;
+  }
+  return v;
+}
+
+template <int N1, int N2>
+void launch_ky(const CbsArgs& a_in, int sign, hipStream_t s) {
   using G = YGeom<N1, N2, kTY>;
+  CbsArgs a = a_in;
+  a.ky_prio = CBS_Y_PRIO > 0 ? ky_low_occupancy<N1, N2>() : 0;
   dim3 grid((unsigned)((long long)((a.nx + kTY - 1) / kTY) * a.nz * 3));
   if (sign < 0)
     hipLaunchKernelGGL((ky_pass<N1, N2, kTY, -1>), grid, dim3(G::THREADS), 0, s, a);
