@@ -173,6 +173,20 @@ def design_bench(args, dev):
         return {"eta_f": num(f["eta_f"]), "fwhm_um": [num(w, 1e6, 3) for w in f["fwhm"]],
                 "focus": list(f["focus"]), "peak": num(f["peak"], 1.0, 3)}
 
+    if args.profile_iters > 0:
+        # the passes on the kinoform start, for rocprofv3 (no optimisation steps)
+        with torch.no_grad():
+            opt.eps[z0:z1] = opt.map(opt.p)
+        opt.plan.set_permittivity(opt.eps)
+        warm = max(1, int(1.0e3 / max(1e-3, sum(opt.plan.time_passes(iters=2, E=opt.E).values()))))
+        opt.plan.time_passes(iters=warm, E=opt.E)
+        passes = opt.plan.time_passes(iters=args.profile_iters, E=opt.E)
+        ms = copy_probe(dev)
+        log(f"[bench] profile mode: {args.profile_iters} iterations of lens32; passes (ms) {passes}; "
+            f"copy probe 1 GiB: {ms:.4f} ms = {2 * 2**30 / ms / 1e6:.0f} GB/s")
+        opt.close()
+        return 0
+
     start = figures()
     log(f"[bench] design start: {start}")
     foms = []
@@ -215,7 +229,8 @@ def design_bench(args, dev):
         "iteration_ms": round(it_ms, 4),
         "passes_ms": {kk: round(v, 4) for kk, v in passes.items()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic_from_profile("lens32", dom),
                      "kernel": dom, "alg_bytes_per_launch": PASS_BYTES[dom] * nvox,
                      "avg_launch_ms": round(passes[dom], 4)},
         "design": {"fom_relative": [round(f / foms[0], 4) for f in foms],
