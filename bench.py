@@ -98,14 +98,22 @@ def copy_probe(dev, nbytes=1 << 30, reps=1):
 SERVE_MAX_ITER = 20000
 
 
-def serving(dev, n_requests: int, load: float, tol: float):
+SERVE_TRACE_LEN = 200   # the configured served stream; shorter runs take its prefix
+
+
+def serving(dev, n_requests: int, loads, tol: float):
     """Served stream of mixed-grid forward/adjoint solves (Poisson arrivals,
-    numpy default_rng(0)): one-at-a-time service time measured first, then the
-    stream at `load` x that service rate, continuous-batched and one at a time."""
+    numpy default_rng(0)): every request is first served back to back, one at
+    a time, which measures its service time; then, for each load, the stream
+    arrives at load x the mean service rate and is served with continuous
+    batching.  One-at-a-time latencies at that load follow from the measured
+    service times by the FIFO recurrence (start = max(arrival, previous
+    finish)): solves are deterministic, so a third pass would repeat them."""
     import dataclasses
     import numpy as np
     from paper_2506_15411_amd import scenes
-    from paper_2506_15411_amd.serve import Server, summarize
+    from paper_2506_15411_amd.serve import (Server, fifo_one_at_a_time, service_times,
+                                            summarize)
     trace = scenes.served_trace(n_requests, 1.0, seed=0)
     unit_arrivals = [r.arrival for r in trace]
     srv = Server(dev, max_active=4, tol=tol, max_iter=SERVE_MAX_ITER)
@@ -118,28 +126,46 @@ def serving(dev, n_requests: int, load: float, tol: float):
         return f
 
     back_to_back = [dataclasses.replace(r, arrival=0.0) for r in trace]
-    t = time.perf_counter()
     b2b = srv.run_sequential(back_to_back, progress=prog("one-at-a-time service"))
-    service = (time.perf_counter() - t) / len(trace)
+    service = service_times(b2b)
+    mean_service = float(np.mean([v.seconds for v in service.values()]))
     per = {}
     for r in b2b:
         per.setdefault(str(r.shape), []).append(sum(r.iterations))
     log(f"[bench] serving iterations per grid: " +
         ", ".join(f"{k}: median {int(np.median(v))} max {max(v)}" for k, v in per.items()))
-    rate = load / service
-    timed = [dataclasses.replace(r, arrival=a / rate) for r, a in zip(trace, unit_arrivals)]
-    log(f"[bench] serving: mean one-at-a-time service {service * 1e3:.1f} ms, rate {rate:.2f}/s")
-    mixed = summarize(srv.run(timed, progress=prog("continuous batching")))
-    seq = summarize(srv.run_sequential(timed, progress=prog("one at a time")))
+    capped = [{"rid": r.rid, "grid": list(r.shape), "kind": r.kind, "iterations": list(r.iterations),
+               "status": r.status} for r in b2b if r.status != 0]
+
+    def rnd(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+    legs = []
+    for load in loads:
+        rate = load / mean_service
+        timed = [dataclasses.replace(r, arrival=a / rate) for r, a in zip(trace, unit_arrivals)]
+        log(f"[bench] serving at load {load}: mean service {mean_service * 1e3:.1f} ms, "
+            f"rate {rate:.3f}/s")
+        mixed = summarize(srv.run(timed, progress=prog(f"continuous batching, load {load}")))
+        seq = summarize(fifo_one_at_a_time(timed, service))
+        legs.append({"load": load, "arrival_rate_hz": round(rate, 4),
+                     "continuous_batching": rnd(mixed), "one_at_a_time": rnd(seq)})
     srv.close()
+    n_label = (f"{len(trace)}" if len(trace) >= SERVE_TRACE_LEN else
+               f"{len(trace)} of {SERVE_TRACE_LEN} (prefix of the seeded stream)")
     return {
-        "requests": len(trace), "load": load, "arrival_rate_hz": round(rate, 3),
+        "requests": n_label,
         "grids": ["64^3 lambda/6", "128^3 lambda/6", "192x192x256 lambda/12", "275x275x315 lambda/16"],
-        "mean_service_s": round(service, 4),
-        "max_iter_per_solve": SERVE_MAX_ITER,
-        "iterations_per_grid": {k: {"median": int(np.median(v)), "max": int(max(v))} for k, v in per.items()},
-        "continuous_batching": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in mixed.items()},
-        "one_at_a_time": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in seq.items()},
+        "tol": tol, "max_iter_per_solve": SERVE_MAX_ITER,
+        "scheduler": {"max_active": srv.max_active, "inflight_quanta": srv.inflight,
+                      "quantum_target_ms": srv.target_ms,
+                      "exclusive_after_s": srv.exclusive_after_s},
+        "mean_service_s": round(mean_service, 4),
+        "one_at_a_time_method": "FIFO recurrence over the measured back-to-back service times",
+        "iterations_per_grid": {k: {"median": int(np.median(v)), "max": int(max(v))}
+                                for k, v in per.items()},
+        "not_converged": capped,
+        "loads": legs,
     }
 
 
@@ -242,32 +268,66 @@ def design_bench(args, dev):
     return 0
 
 
-def cpu_baseline(sc):
-    """FP64 oracle on the host: one CBS iteration of the same workload.
+def cpu_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import psutil
+        phys = psutil.cpu_count(logical=False)
+    except Exception:
+        phys = None
+    return model, phys, os.cpu_count()
 
-    The oracle's own setup (potentials) is timed separately and subtracted
-    from one oracle call with max_iter = 1."""
+
+def cpu_baseline(sc, samples: int = 5):
+    """FP64 oracle on the host: one CBS iteration of the same workload, timed
+    as one warm-up and then the median of `samples` timings.  Each timing is
+    one oracle call with max_iter = 1 minus the oracle's own set-up (the
+    potentials), timed just before it."""
+    import statistics
     from oracle import cbs as oc
     g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
     eps = sc.eps_r
     S = oc.plane_wave_source(g, eps)
-    t0 = time.perf_counter()
-    pot = oc.potentials(g, eps)
-    t1 = time.perf_counter()
-    del pot
-    t2 = time.perf_counter()
-    r = oc.cbs(g, eps, S, tol=0.0, max_iter=1)
-    t3 = time.perf_counter()
-    del r, S
-    per_it = (t3 - t2) - (t1 - t0)
+    r = oc.cbs(g, eps, S, tol=0.0, max_iter=1)          # warm-up
+    del r
+    times = []
+    for k in range(samples):
+        t0 = time.perf_counter()
+        pot = oc.potentials(g, eps)
+        t1 = time.perf_counter()
+        del pot
+        t2 = time.perf_counter()
+        r = oc.cbs(g, eps, S, tol=0.0, max_iter=1)
+        t3 = time.perf_counter()
+        del r
+        times.append((t3 - t2) - (t1 - t0))
+        log(f"[bench] oracle iteration sample {k + 1}/{samples}: {times[-1]:.2f} s")
+    med = statistics.median(times)
+    model, phys, logical = cpu_info()
     return {
-        "value": round(sc.n_vox / per_it / 1e9, 6),
+        "value": round(sc.n_vox / med / 1e9, 6),
         "unit": "Gvoxel-iter/s",
         "cores": oc._WORKERS,
         "kind": "oracle",
         "sample": (f"one FP64 oracle CBS iteration on the full {sc.shape[0]}x{sc.shape[1]}x"
-                   f"{sc.shape[2]} volume: {per_it:.1f} s (oracle setup, {t1 - t0:.1f} s, "
-                   f"timed separately and excluded)"),
+                   f"{sc.shape[2]} volume: one warm-up, then the median of {samples} "
+                   f"(oracle set-up timed separately and excluded)"),
+        "samples": samples,
+        "median_s": round(med, 3),
+        "all_s": [round(t, 3) for t in times],
+        "cpu_model": model,
+        "physical_cores": phys,
+        "logical_cpus": logical,
+        "threads_note": (f"scipy.fft uses {oc._WORKERS} workers; numpy's elementwise "
+                         f"operations run on one thread"),
     }
 
 
@@ -287,9 +347,14 @@ def main(argv=None):
     ap.add_argument("--check-every", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=40,
-                    help="requests in the served mixed-grid stream (0 = skip serving)")
-    ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="arrival rate as a fraction of the one-at-a-time service rate")
+                    help="requests of the seeded 200-request served stream to replay (its "
+                         "prefix; 0 = skip serving)")
+    ap.add_argument("--serve-loads", default="0.7",
+                    help="comma-separated arrival rates as fractions of the one-at-a-time "
+                         "service rate")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg and print its JSON")
+    ap.add_argument("--serve-out", default=None, help="also write the serving JSON here")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling mode: about 1 s of warm-up iterations, then this many "
                          "CBS iterations of the workload (one launch of each pass per "
@@ -311,12 +376,21 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 1
     dev = torch.device("cuda:0")
+    loads = [float(v) for v in args.serve_loads.split(",") if v]
+    if args.serve_only:
+        res = serving(dev, args.serve_requests, loads, args.tol)
+        if args.serve_out:
+            with open(args.serve_out, "w") as f:
+                json.dump(res, f, indent=1)
+        print(json.dumps({"serving": res}), flush=True)
+        return 0
     if args.workload == "lens32":
         return design_bench(args, dev)
     log(f"[bench] building scene {args.workload}")
     sc = workload(args.workload)
     eps = torch.from_numpy(sc.eps_r).to(dev)
     plan = Plan(sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml, device=dev)
+    plan_order, plan_sigma, plan_kappa = 2, 1.0, 1.1     # the Plan defaults
     E = plan.new_field()
     Ea = plan.new_field()
     lo, hi = sc.design_box
@@ -384,7 +458,8 @@ def main(argv=None):
                                f"pitch {sc.pitch * 1e9:.1f} nm: forward + adjoint CBS (tol "
                                f"{args.tol:g}) + gradient over the design slab",
                    "voxels": nvox, "iterations_per_step": iters / args.steps,
-                   "tol": args.tol, "shift_factor": 1.1, "pml_per_side": list(sc.pml)},
+                   "tol": args.tol, "shift_factor": plan_kappa, "pml_per_side": list(sc.pml),
+                   "pml_order": plan_order, "sigma_max": plan_sigma},
         "hbm_frac_iteration": round(ITER_BYTES * nvox / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "iteration_ms": round(it_ms, 3),
         "solve_only_gvoxel_iter_s": round(iter_rate, 3),
@@ -399,10 +474,13 @@ def main(argv=None):
         plan.close()
         del plan
         torch.cuda.empty_cache()
-        out["serving"] = serving(dev, args.serve_requests, args.serve_load, args.tol)
-        if out["serving"]:
-            out["p50_served_latency_s"] = out["serving"]["continuous_batching"]["p50_latency_s"]
-            out["p99_served_latency_s"] = out["serving"]["continuous_batching"]["p99_latency_s"]
+        out["serving"] = serving(dev, args.serve_requests, loads, args.tol)
+        if args.serve_out:
+            with open(args.serve_out, "w") as f:
+                json.dump(out["serving"], f, indent=1)
+        leg = out["serving"]["loads"][0]
+        out["p50_served_latency_s"] = leg["continuous_batching"]["p50_latency_s"]
+        out["p99_served_latency_s"] = leg["continuous_batching"]["p99_latency_s"]
     if not args.no_cpu_baseline:
         torch.cuda.empty_cache()
         log("[bench] timing the FP64 oracle on the host")

@@ -58,7 +58,11 @@ enum {
   CBS_SRC_NONE = 0,        /* S = 0 */
   CBS_SRC_PLANE_WAVE = 1,  /* S = k0^2 (eps_r - n_bg^2) pol exp(i kb z), +z incidence  */
   CBS_SRC_FIELD = 2,       /* S = field (device complex64 [3][nz][ny][nx], units 1/m^2) */
-  CBS_SRC_POINT = 3        /* S = amp at voxel r0, zero elsewhere (units 1/m^2)        */
+  CBS_SRC_POINT = 3,       /* S = amp at voxel r0, zero elsewhere (units 1/m^2)        */
+  CBS_SRC_FIELD_CONJ = 4   /* S = conj(field), field as for FIELD: the adjoint source
+                              conj(gE) of a loss whose derivative gE = 2 dL/dE* is held
+                              in device memory (optimisation paragraph: the gradient
+                              through one more CBS solve); conjugated on the device   */
 };
 
 enum {
@@ -89,7 +93,7 @@ typedef struct {
   int kind;                 /* CBS_SRC_*                                              */
   double pol[3][2];         /* PLANE_WAVE: polarisation (re, im) per component;
                                all zero means x-polarised                             */
-  const void* field;        /* FIELD: device complex64 [3][nz][ny][nx]                */
+  const void* field;        /* FIELD, FIELD_CONJ: device complex64 [3][nz][ny][nx]    */
   int r0[3];                /* POINT: voxel (ix, iy, iz)                              */
   double amp[3][2];         /* POINT: amplitude (re, im) per component                */
 } cbs_source;
@@ -151,7 +155,8 @@ int cbs_solve(cbs_plan_t plan, const cbs_source* src, void* E_dev,
  *   adj_src POINT with E_fwd_dev != NULL: g = conj(E_fwd(r0)) at r0, built on
  *           the device (gradient of |E(r0)|^2 with scale 2 in cbs_gradient);
  *   adj_src POINT with E_fwd_dev == NULL: g = adj_src->amp at r0;
- *   adj_src FIELD: g = adj_src->field.
+ *   adj_src FIELD: g = adj_src->field;
+ *   adj_src FIELD_CONJ: g = conj(adj_src->field).
  * E_adj_dev receives complex64 [3][nz][ny][nx].  Synchronises the stream. */
 int cbs_adjoint_solve(cbs_plan_t plan, const void* E_fwd_dev, const cbs_source* adj_src,
                       void* E_adj_dev, const cbs_opts* opts, cbs_stats* stats);

@@ -183,9 +183,9 @@ __global__ void k_point_amp(DevState* st, const float2* E, long long idx, long l
 constexpr int kResThreads = 256;
 __global__ void __launch_bounds__(kResThreads)
 k_residual(const double* part, int nb, DevState* st, double* hist) {
-  __shared__ double s0[kResThreads], s1[kResThreads];
+  __shared__ double red[2 * kResStreams];
   if (st->done || !st->pending) return;
-  residual_finish<kResThreads>(part, nb, st, hist, s0, s1);
+  residual_finish<kResThreads>(part, nb, st, hist, red);
   if (threadIdx.x == 0) st->pending = 0;
 }
 
@@ -555,11 +555,7 @@ int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
   p->oy->ky(a, -1, p->stream);
   p->oz->kz(a, p->stream);
   p->oy->ky(a, +1, p->stream);
-  p->ox->k1(a, K1_ITER, p->stream);
-  if (!CBS_LAG_RESIDUAL) {
-    hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
-                       p->k1_blocks, p->state, p->hist);
-  }
+  p->ox->k1(a, K1_ITER, p->stream);   // its residual is reduced by the next y pass
   HIP_LAUNCHED();
   return CBS_OK;
 }
@@ -742,8 +738,9 @@ int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, f
       break;
     }
     case CBS_SRC_FIELD:
+    case CBS_SRC_FIELD_CONJ:
       if (!src->field) return fail(CBS_E_INVALID, "FIELD source without a field pointer");
-      a.src = SRC_FIELD;
+      a.src = kind == CBS_SRC_FIELD ? SRC_FIELD : SRC_FIELD_CONJ;
       a.fin = static_cast<const float2*>(src->field);
       break;
     case CBS_SRC_POINT:
@@ -774,8 +771,9 @@ int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cb
   if (!E) return fail(CBS_E_INVALID, "output field is NULL");
   if (adjoint) {
     if (!src) return fail(CBS_E_INVALID, "adjoint source is NULL");
-    if (src->kind != CBS_SRC_POINT && src->kind != CBS_SRC_FIELD)
-      return fail(CBS_E_INVALID, "adjoint source must be POINT or FIELD");
+    if (src->kind != CBS_SRC_POINT && src->kind != CBS_SRC_FIELD &&
+        src->kind != CBS_SRC_FIELD_CONJ)
+      return fail(CBS_E_INVALID, "adjoint source must be POINT, FIELD or FIELD_CONJ");
   }
   a = base_args(p);
   if ((rc = set_source(p, a, src, adjoint != 0, pol))) return rc;
@@ -1229,10 +1227,7 @@ int cbs_time_passes(cbs_plan_t p, void* E_dev, int iters, float* ms_out) {
     HIP_TRY(hipEventRecord(p->evp[3], p->stream));
     p->ox->k1(a, K1_ITER, p->stream);
     HIP_TRY(hipEventRecord(p->evp[4], p->stream));
-    if (!CBS_LAG_RESIDUAL)   // else the next y pass reduces it, as in a solve
-      hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
-                         p->k1_blocks, p->state, p->hist);
-    HIP_LAUNCHED();
+    HIP_LAUNCHED();   // the next y pass reduces the residual, as in a solve
     HIP_TRY(hipEventRecord(p->evp[5], p->stream));
     HIP_TRY(hipEventSynchronize(p->evp[5]));
     for (int k = 0; k < 5; ++k) {

@@ -40,7 +40,7 @@
 
 namespace cbs {
 
-enum SrcKind : int { SRC_NONE = 0, SRC_PLANE = 1, SRC_FIELD = 2, SRC_POINT = 3 };
+enum SrcKind : int { SRC_NONE = 0, SRC_PLANE = 1, SRC_FIELD = 2, SRC_POINT = 3, SRC_FIELD_CONJ = 4 };
 enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
 
 constexpr int kHistCap = 1 << 16;
@@ -52,45 +52,10 @@ constexpr int kHistCap = 1 << 16;
 // 128-byte line), and R consecutive rows of an x-line form 64 R-byte pieces.
 constexpr int kBrick = 8;
 
-// Tuning knobs (compile-time; the defaults are the measured best on gfx950)
-#ifndef CBS_K1_PREFETCH
-#define CBS_K1_PREFETCH 2    // x-pass: 1 = load V0, 2 = load V0 and E_s before the inverse FFT
-#endif
-#ifndef CBS_K1_PF_E
-#define CBS_K1_PF_E 1024     // x-pass: how many of a thread's E_s elements the early load covers
-#endif
-#ifndef CBS_K1_PF_V
-#define CBS_K1_PF_V 1024     // x-pass: how many of a thread's V0 elements the early load covers
-#endif
-#ifndef CBS_Y_TW_GLOBAL
-#define CBS_Y_TW_GLOBAL 0    // y pass: read twiddles from global memory (frees LDS for a 4th block)
-#endif
-#ifndef CBS_K1_ROWS
-#define CBS_K1_ROWS 0        // x-pass: rows of one component per workgroup (0: per-size rule)
-#endif
-#ifndef CBS_KZ_TX
-#define CBS_KZ_TX 0          // z-pass: columns per workgroup, 8 or 4 (0: per-size rule)
-#endif
-#ifndef CBS_TW_STAGED
-#define CBS_TW_STAGED 1      // y and z passes: load the twiddle table alongside the first
-                             // data loads (0: fill it first, one dependent load per entry)
-#endif
-#ifndef CBS_K1_TW
-#define CBS_K1_TW 2          // x-pass twiddle table: 0 = fill loop, 1 = all entries loaded at
-                             // once and written before the operand loads, 2 = staged as above
-#endif
-#ifndef CBS_LOAD_PRIO
-#define CBS_LOAD_PRIO 2      // x-pass wave priority while a work-group issues its first loads,
-                             // used where the iteration kernel holds at most two waves per SIMD
-#endif
-#ifndef CBS_Y_PRIO
-#define CBS_Y_PRIO 2         // y pass: the same load-phase priority where it holds at most
-                             // three waves per SIMD (0: never)
-#endif
-#ifndef CBS_LAG_RESIDUAL
-#define CBS_LAG_RESIDUAL 1   // the first y-pass block of the next iteration finishes the
-                             // residual reduction (no separate launch per iteration)
-#endif
+// Wave priority a pass raises to while its work-groups issue their first
+// loads, where few waves share a SIMD (x pass: at most two, y pass: at most
+// three; the launchers decide from the occupancy API).
+constexpr int kLoadPrio = 2;
 
 // Device-resident solve state (lives in the workspace).
 struct DevState {
@@ -105,46 +70,62 @@ struct DevState {
   int pending;     // the x pass wrote residual partials that are not reduced yet
 };
 
-// Fixed-order sum of the per-block partials, then the stopping rule.  Run by
-// one block (THREADS threads); deterministic whatever block runs it.
+// Fixed-order sum of the per-block partials, then the stopping rule.  The
+// partials are summed in kResStreams interleaved streams (stream s takes
+// partials s, s + kResStreams, ... in order), the stream sums are combined by
+// one wave in a fixed order, so the result is the same double whichever kernel
+// and block shape runs it (the lagged reduction in the y pass and the
+// quantum-end k_residual must agree bit for bit: which of them reduces a given
+// iteration depends on where the host's quanta end).  red holds 2 kResStreams
+// doubles of LDS; THREADS is any multiple of 64.
+constexpr int kResStreams = 256;
 template <int THREADS>
 __device__ __forceinline__ void residual_finish(const double* part, int nb, DevState* st,
-                                                double* hist, double* s0, double* s1) {
-  double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += THREADS) {
-    a += __builtin_nontemporal_load(part + 2 * i);
-    b += __builtin_nontemporal_load(part + 2 * i + 1);
-  }
-  s0[threadIdx.x] = a;
-  s1[threadIdx.x] = b;
-  __syncthreads();
-  for (int w = THREADS / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) {
-      s0[threadIdx.x] += s0[threadIdx.x + w];
-      s1[threadIdx.x] += s1[threadIdx.x + w];
+                                                double* hist, double* red) {
+  static_assert(THREADS % 64 == 0, "whole waves");
+  for (int s = threadIdx.x; s < kResStreams; s += THREADS) {
+    double a = 0.0, b = 0.0;
+    for (int i = s; i < nb; i += kResStreams) {
+      a += __builtin_nontemporal_load(part + 2 * i);
+      b += __builtin_nontemporal_load(part + 2 * i + 1);
     }
-    __syncthreads();
+    red[s] = a;
+    red[kResStreams + s] = b;
   }
-  if (threadIdx.x == 0) {
-    const double nd = s0[0], ne = s1[0];
-    double eta;
-    if (ne > 0.0)
-      eta = sqrt(nd / ne);
-    else
-      eta = (nd == 0.0) ? 0.0 : INFINITY;
-    const int it = st->iter + 1;
-    st->iter = it;
-    st->eta = eta;
-    if (st->record && it <= kHistCap) hist[it - 1] = eta;
-    if (!isfinite(eta)) {
-      st->status = 3;
-      st->done = 1;
-    } else if (eta <= st->tol) {
-      st->status = 1;
-      st->done = 1;
-    } else if (it >= st->max_iter) {
-      st->status = 2;
-      st->done = 1;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x;
+    double nd = red[l], ne = red[kResStreams + l];
+    #pragma unroll
+    for (int q = 64; q < kResStreams; q += 64) {
+      nd += red[l + q];
+      ne += red[kResStreams + l + q];
+    }
+    #pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      nd += __shfl_xor(nd, o, 64);
+      ne += __shfl_xor(ne, o, 64);
+    }
+    if (l == 0) {
+      double eta;
+      if (ne > 0.0)
+        eta = sqrt(nd / ne);
+      else
+        eta = (nd == 0.0) ? 0.0 : INFINITY;
+      const int it = st->iter + 1;
+      st->iter = it;
+      st->eta = eta;
+      if (st->record && it <= kHistCap) hist[it - 1] = eta;
+      if (!isfinite(eta)) {
+        st->status = 3;
+        st->done = 1;
+      } else if (eta <= st->tol) {
+        st->status = 1;
+        st->done = 1;
+      } else if (it >= st->max_iter) {
+        st->status = 2;
+        st->done = 1;
+      }
     }
   }
 }
@@ -194,7 +175,6 @@ constexpr int round64(int t) { return (t + 63) / 64 * 64; }
 // best at R = 4, 275 = 25 x 11 at R = 5; three-wave groups of R = 7 lose a
 // quarter of the occupancy and run 10% slower).
 constexpr int k1_rows_for(int tm) {
-  if (CBS_K1_ROWS > 0) return CBS_K1_ROWS;
   int best = 1;
   for (int r = 2; r <= 8 && r * tm <= 128; ++r)
     if (r * tm * round64(best * tm) >= best * tm * round64(r * tm)) best = r;
@@ -207,7 +187,6 @@ constexpr int k1_rows_for(int tm) {
 // 0.46 ms with 8; split 15 x 21, 8 waves per workgroup, 0.27 ms with 8 columns
 // against 0.34 ms with 4).
 constexpr int kz_tx_for(int n1, int n2) {
-  if (CBS_KZ_TX > 0) return CBS_KZ_TX;
   const int n = n1 * n2;
   const int lds8 = 3 * n * 8 * 8 + n * 8;
   if (lds8 <= 53 * 1024) return 8;
@@ -329,15 +308,10 @@ k1_xpass(CbsArgs a) {
   const int tid = threadIdx.x;
   // with few waves per SIMD, a work-group's load phase would otherwise wait
   // behind the other waves' vector work
-  if (CBS_LOAD_PRIO > 0 && a.k1_prio) __builtin_amdgcn_s_setprio(CBS_LOAD_PRIO);
+  if (a.k1_prio) __builtin_amdgcn_s_setprio(kLoadPrio);
   __shared__ float2 tw[N];
   TwStage<N, G::THREADS> tws;
-  if constexpr (CBS_K1_TW == 0) {
-    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twx[i];
-  } else {
-    tws.issue(a.twx, tid);
-    if constexpr (CBS_K1_TW == 1) tws.commit(tw, tid);
-  }
+  tws.issue(a.twx, tid);
 
   // block -> (component, row group, z); the three components of the same rows
   // are adjacent in the remapped order so V0 is shared in one L2
@@ -361,20 +335,17 @@ k1_xpass(CbsArgs a) {
   const long long vbase = ((long long)z * a.ny + y) * a.nx;             // V0 row
 
   float2 v[N2];  // thread t (< N1): element t + N1 m, m < N2
-  // early loads of the pointwise operands (their latency hides behind the
-  // inverse transform)
-  constexpr bool PF_V = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 1;
-  constexpr bool PF_E = (MODE == K1_ITER) && CBS_K1_PREFETCH >= 2;
-  constexpr int kPfE = PF_E ? (CBS_K1_PF_E < N2 ? CBS_K1_PF_E : N2) : 0;
-  constexpr int kPfV = PF_V ? (CBS_K1_PF_V < N2 ? CBS_K1_PF_V : N2) : 0;
-  float2 pv[kPfV > 0 ? kPfV : 1], pe[kPfE > 0 ? kPfE : 1];
+  // early loads of the pointwise operands V0 and E_s (their latency hides
+  // behind the inverse transform)
+  constexpr bool PF = (MODE == K1_ITER);
+  float2 pv[PF ? N2 : 1], pe[PF ? N2 : 1];
   const float2* v0t = a.V0 + vbase + t;   // this thread's elements are t + N1 m
   float2* et = a.E + ebase + t;
-  if constexpr (PF_V) {
-    if (ok && t < N1) sfor<0, kPfV>([&](auto M) { pv[CV(M)] = v0t[N1 * CV(M)]; });
-  }
-  if constexpr (PF_E) {
-    if (ok && t < N1) sfor<0, kPfE>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
+  if constexpr (PF) {
+    if (ok && t < N1) {
+      sfor<0, N2>([&](auto M) { pv[CV(M)] = v0t[N1 * CV(M)]; });
+      sfor<0, N2>([&](auto M) { pe[CV(M)] = et[N1 * CV(M)]; });
+    }
   }
 
   // element x of this thread's row in the bricks
@@ -385,14 +356,12 @@ k1_xpass(CbsArgs a) {
   auto load_a = [&]() {
     if (ok && t < N2) sfor<0, N1>([&](auto J1) { b[CV(J1)] = wat(t + N2 * CV(J1)); });
   };
-  constexpr bool kStaged = CBS_K1_TW == 2;
-  if constexpr (MODE != K1_FWD && kStaged) load_a();
-  if constexpr (kStaged) tws.commit(tw, tid);
+  if constexpr (MODE != K1_FWD) load_a();
+  tws.commit(tw, tid);
   __syncthreads();   // the twiddle table is in LDS
-  if (CBS_LOAD_PRIO > 0 && a.k1_prio) __builtin_amdgcn_s_setprio(0);
+  if (a.k1_prio) __builtin_amdgcn_s_setprio(0);
 
   if constexpr (MODE != K1_FWD) {
-    if constexpr (!kStaged) load_a();
     // inverse level A: DFT-N1 over row[j2 + N2 j1]
     if (ok && t < N2) {
       dft<N1, +1>(b);
@@ -427,9 +396,9 @@ k1_xpass(CbsArgs a) {
       const int x = t + N1 * CV(M);
       float2 e;
       float2 v0;
-      if constexpr (CV(M) < kPfV) v0 = pv[CV(M)]; else v0 = v0t[N1 * CV(M)];
+      if constexpr (PF) v0 = pv[CV(M)]; else v0 = v0t[N1 * CV(M)];
       if constexpr (MODE == K1_ITER) {
-        if constexpr (CV(M) < kPfE) e = pe[CV(M)]; else e = et[N1 * CV(M)];
+        e = pe[CV(M)];
         // gamma = 1 + i V0 / eps
         const float2 gm = make_float2(1.0f - v0.y * a.inv_eps, v0.x * a.inv_eps);
         const float2 d = cmul(gm, csub(v[CV(M)], e));
@@ -455,6 +424,9 @@ k1_xpass(CbsArgs a) {
           if (xin && yin && zin) w = cadd(w, cmul(v0, spl));
         } else if (a.src == SRC_FIELD) {
           w = cadd(w, cscale(a.fin[ebase + x], a.src_scale));
+        } else if (a.src == SRC_FIELD_CONJ) {
+          const float2 f = a.fin[ebase + x];
+          w = cadd(w, make_float2(f.x * a.src_scale, -f.y * a.src_scale));
         } else if (a.src == SRC_POINT) {
           if (x == a.r0x && y == a.r0y && z == a.r0z) w = cadd(w, a.st->amp[c]);
         }
@@ -489,36 +461,26 @@ ky_pass(CbsArgs a) {
   using G = YGeom<N1, N2, TX>;
   constexpr int N = G::N;
   __shared__ float2 lds[N * TX];
-#if CBS_Y_TW_GLOBAL
-  const float2* tw = a.twy;
-#else
   __shared__ float2 tw[N];
-#endif
   if (a.st->done) return;
   const int tid = threadIdx.x;
-  if (CBS_Y_PRIO > 0 && a.ky_prio) __builtin_amdgcn_s_setprio(CBS_Y_PRIO);
-  if (CBS_LAG_RESIDUAL && S < 0 && blockIdx.x == 0 && a.st->pending) {
+  if (a.ky_prio) __builtin_amdgcn_s_setprio(kLoadPrio);
+  if (S < 0 && blockIdx.x == 0 && a.st->pending) {
     // finish the previous iteration's residual (stream order: the x pass that
     // wrote the partials has completed); lds is still unused here
-    constexpr bool kFits = sizeof(lds) >= 2 * G::THREADS * sizeof(double);
+    constexpr bool kFits = sizeof(lds) >= 2 * kResStreams * sizeof(double);
     if constexpr (kFits) {
-      double* s0 = reinterpret_cast<double*>(lds);
-      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, s0, s0 + G::THREADS);
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist,
+                                  reinterpret_cast<double*>(lds));
     } else {
-      __shared__ double s0[G::THREADS], s1[G::THREADS];
-      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, s0, s1);
+      __shared__ double red[2 * kResStreams];
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, red);
     }
     if (tid == 0) a.st->pending = 0;
     __syncthreads();
   }
-#if !CBS_Y_TW_GLOBAL
   TwStage<N, G::THREADS> tws;
-  if constexpr (CBS_TW_STAGED) {
-    tws.issue(a.twy, tid);
-  } else {
-    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twy[i];
-  }
-#endif
+  tws.issue(a.twy, tid);
   const int xi = tid % TX;
   const int t = tid / TX;
   const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
@@ -545,13 +507,10 @@ ky_pass(CbsArgs a) {
       }
     }
   };
-  if constexpr (CBS_TW_STAGED) load_a();
-#if !CBS_Y_TW_GLOBAL
-  if constexpr (CBS_TW_STAGED) tws.commit(tw, tid);
-#endif
+  load_a();
+  tws.commit(tw, tid);
   __syncthreads();
-  if (CBS_Y_PRIO > 0 && a.ky_prio) __builtin_amdgcn_s_setprio(0);
-  if constexpr (!CBS_TW_STAGED) load_a();
+  if (a.ky_prio) __builtin_amdgcn_s_setprio(0);
   if (t < N2) {
     dft<N1, S>(b);
     const float2* twt = tw + t * N1;
@@ -585,11 +544,7 @@ kz_pass(CbsArgs a) {
   if (a.st->done) return;
   const int tid = threadIdx.x;
   TwStage<N, G::THREADS> tws;
-  if constexpr (CBS_TW_STAGED) {
-    tws.issue(a.twz, tid);
-  } else {
-    for (int i = tid; i < N; i += G::THREADS) tw[i] = a.twz[i];
-  }
+  tws.issue(a.twz, tid);
   const int xi = tid % TX;
   const int t = tid / TX;
   // remapped order: the kBrick / TX parts of one brick row, then y, then the
@@ -621,12 +576,9 @@ kz_pass(CbsArgs a) {
       }
     }
   };
-  if constexpr (CBS_TW_STAGED) {
-    load_a();
-    tws.commit(tw, tid);
-  }
+  load_a();
+  tws.commit(tw, tid);
   __syncthreads();
-  if constexpr (!CBS_TW_STAGED) load_a();
   if (t < 3 * N2) {
     dft<N1, -1>(b);
     const float2* twt = tw + j2 * N1;
@@ -818,7 +770,7 @@ template <int N1, int N2>
 void launch_ky(const CbsArgs& a_in, int sign, hipStream_t s) {
   using G = YGeom<N1, N2, kTY>;
   CbsArgs a = a_in;
-  a.ky_prio = CBS_Y_PRIO > 0 ? ky_low_occupancy<N1, N2>() : 0;
+  a.ky_prio = ky_low_occupancy<N1, N2>();
   dim3 grid((unsigned)((long long)((a.nx + kTY - 1) / kTY) * a.nz * 3));
   if (sign < 0)
     hipLaunchKernelGGL((ky_pass<N1, N2, kTY, -1>), grid, dim3(G::THREADS), 0, s, a);

@@ -30,6 +30,7 @@ CBS_SRC_NONE = 0
 CBS_SRC_PLANE_WAVE = 1
 CBS_SRC_FIELD = 2
 CBS_SRC_POINT = 3
+CBS_SRC_FIELD_CONJ = 4
 
 CBS_WARM_START = 1
 CBS_RETURN_SCATTERED = 2

@@ -15,6 +15,16 @@ material in the absorbing layer) or whose solve diverges (non-finite residual)
 fails alone: its result carries the library's negative status, no fields or
 gradient, and the other requests are served as if it had not been there.
 
+Scheduling.  Admission is in arrival order while a slot and HBM are free.
+Active solves advance in quanta of about 4 ms of device work, each on its own
+stream.  A request whose solve has run for longer than `exclusive_after_s`
+since admission is given the device alone: no new request is admitted and the
+other active solves get no further quanta until it completes (their queued
+quanta drain).  One large solve saturates HBM by itself, so sharing the device
+with it only stretches it; short requests keep overlapping freely.  This keeps
+the latency of the few long solves near their one-at-a-time service time while
+the many short ones are served concurrently.
+
 Latency is arrival -> result complete in device memory.
 """
 
@@ -64,8 +74,19 @@ class _Slot:
             self.Ea = self.plan.new_field()
             nx, ny, nz = shape
             self.eps = torch.empty((nz, ny, nx), dtype=torch.float32, device=device)
+        # pinned staging buffer: a request's permittivity is uploaded without a
+        # pageable (blocking) copy
+        self.eps_host = torch.empty((nz, ny, nx), dtype=torch.float32, pin_memory=True)
         self.nbytes = slot_bytes(shape)
         self.last_used = 0.0
+
+    def upload(self, eps_r: np.ndarray):
+        """Stage eps_r in pinned memory and copy it on the slot's stream (the
+        previous use of the staging buffer completed: set_permittivity
+        synchronises the stream)."""
+        self.eps_host.numpy()[...] = eps_r
+        with torch.cuda.stream(self.stream):
+            self.eps.copy_(self.eps_host, non_blocking=True)
 
     def close(self):
         self.plan.close()
@@ -107,7 +128,7 @@ class Server:
 
     def __init__(self, device=None, max_active: int = 4, budget_bytes: int | None = None,
                  tol: float = 1e-4, max_iter: int = 20000, inflight: int = 2,
-                 target_ms: float = 4.0):
+                 target_ms: float = 4.0, exclusive_after_s: float | None = 1.0):
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -118,6 +139,7 @@ class Server:
         self.max_iter = max_iter
         self.inflight = inflight
         self.target_ms = target_ms
+        self.exclusive_after_s = exclusive_after_s
         self.idle = collections.defaultdict(list)   # key -> [_Slot]
         self.used = 0
         self.refused = 0
@@ -163,8 +185,7 @@ class Server:
     def _start(self, job: _Job):
         s = job.slot
         sc = job.req.scene
-        with torch.cuda.stream(s.stream):
-            s.eps.copy_(torch.from_numpy(sc.eps_r), non_blocking=False)
+        s.upload(sc.eps_r)
         s.plan.set_permittivity(s.eps)
         s.plan.begin(s.E, tol=self.tol, max_iter=self.max_iter)
         for _ in range(self.inflight):
@@ -228,7 +249,12 @@ class Server:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 waiting.append(pending.popleft())
-            while waiting and len(active) < self.max_active:
+            # the oldest active solve, once long-running, has the device alone
+            excl = None
+            if active and self.exclusive_after_s is not None \
+                    and now - active[0].admitted > self.exclusive_after_s:
+                excl = active[0]
+            while excl is None and waiting and len(active) < self.max_active:
                 slot = self._acquire(waiting[0].scene, now)
                 if slot is None:
                     self.refused += 1
@@ -261,7 +287,7 @@ class Server:
                             progress(results[-1], len(results))
                         active.remove(job)
                         self._release(job.slot, time.perf_counter() - t0)
-                elif outstanding < self.inflight:
+                elif outstanding < self.inflight and (excl is None or job is excl):
                     job.slot.plan.advance(job.quantum)
                     progressed = True
             if not progressed:
@@ -283,8 +309,7 @@ class Server:
             if slot is None:
                 raise RuntimeError("no memory for a sequential slot")
             p = slot.plan
-            with torch.cuda.stream(slot.stream):
-                slot.eps.copy_(torch.from_numpy(r.scene.eps_r))
+            slot.upload(r.scene.eps_r)
             its = (0, 0)
             grad = None
             try:
@@ -318,6 +343,35 @@ class Server:
             if progress is not None:
                 progress(res, len(results))
         return results
+
+
+def fifo_one_at_a_time(requests, service: dict) -> list:
+    """Results of serving `requests` one at a time in arrival order, from each
+    request's measured service time (service[rid], from a back-to-back
+    run_sequential pass): each starts at max(its arrival, the previous finish).
+    Solves are deterministic (fixed-order reductions, device-side stopping
+    rule), so a request's service time does not depend on when it runs."""
+    out = []
+    t = 0.0
+    for r in sorted(requests, key=lambda r: r.arrival):
+        sv = service[r.rid]
+        start = max(r.arrival, t)
+        t = start + sv.seconds
+        out.append(ServedResult(r.rid, r.kind, tuple(r.scene.shape), sv.status, sv.iterations,
+                                r.arrival, start, t))
+    return out
+
+
+@dataclasses.dataclass
+class ServiceTime:
+    seconds: float
+    status: int
+    iterations: tuple
+
+
+def service_times(results) -> dict:
+    """rid -> service time of a back-to-back run_sequential pass."""
+    return {r.rid: ServiceTime(r.finished - r.admitted, r.status, r.iterations) for r in results}
 
 
 def summarize(results, wall_s: float | None = None) -> dict:

@@ -77,7 +77,10 @@ class Plan:
         return (3,) + self.vshape
 
     def new_field(self):
-        return torch.zeros(self.fshape, dtype=torch.complex64, device=self.device)
+        """A zeroed complex64 [3, nz, ny, nx] field, allocated and cleared on the
+        plan's stream so the plan's kernels are ordered after the clear."""
+        with torch.cuda.stream(self.stream):
+            return torch.zeros(self.fshape, dtype=torch.complex64, device=self.device)
 
     # -- entry points -----------------------------------------------------------
     def set_permittivity(self, eps_r: torch.Tensor):
@@ -103,6 +106,8 @@ class Plan:
         src = L.cbs_source()
         if field is not None:
             _require_gpu(field, "field", torch.complex64, self.fshape)
+            if field.is_conj():
+                raise ValueError("field has torch's lazy conjugate bit; resolve it first")
             src.kind = L.CBS_SRC_FIELD
             src.field = field.data_ptr()
         elif point is not None:
@@ -120,12 +125,15 @@ class Plan:
                     src.pol[c][0], src.pol[c][1] = a.real, a.imag
         return src
 
-    def _adjoint_source(self, E_fwd=None, r0=None, amp=None, field=None):
+    def _adjoint_source(self, E_fwd=None, r0=None, amp=None, field=None, conj=False):
         src = L.cbs_source()
         fptr = 0
         if field is not None:
             _require_gpu(field, "field", torch.complex64, self.fshape)
-            src.kind = L.CBS_SRC_FIELD
+            if field.is_conj():
+                raise ValueError("field has torch's lazy conjugate bit; pass conj=True "
+                                 "with the unconjugated tensor instead")
+            src.kind = L.CBS_SRC_FIELD_CONJ if conj else L.CBS_SRC_FIELD
             src.field = field.data_ptr()
         else:
             src.kind = L.CBS_SRC_POINT
@@ -155,14 +163,15 @@ class Plan:
 
     def adjoint(self, E_fwd: torch.Tensor | None = None, r0=None, amp=None, field=None,
                 E_adj: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
-                warm=False, history=False):
+                warm=False, history=False, conj=False):
         """Adjoint solve.  With r0 and E_fwd: source conj(E_fwd(r0)) at r0
         (objective |E(r0)|^2).  With r0 and amp: that amplitude.  With field:
-        a general source.  Returns (E_adj, SolveStats)."""
+        a general source (conj=True: its complex conjugate, formed on the
+        device).  Returns (E_adj, SolveStats)."""
         if E_adj is None:
             E_adj = self.new_field()
         _require_gpu(E_adj, "E_adj", torch.complex64, self.fshape)
-        src, fptr = self._adjoint_source(E_fwd, r0, amp, field)
+        src, fptr = self._adjoint_source(E_fwd, r0, amp, field, conj)
         rc, st = L.cbs_adjoint_solve(self.handle, fptr, src, E_adj.data_ptr(),
                                      self._opts(tol, max_iter, check_every, warm, False, history))
         return E_adj, _stats(rc, st)

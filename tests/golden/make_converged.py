@@ -1,0 +1,182 @@
+"""Writes the converged-solution fixtures of the GPU parity tests.
+
+Calls only the FP64 oracle (``oracle/``) and the seeded scene generator
+(``paper_2506_15411_amd.scenes``, geometry and random numbers only).  Nothing
+here reads anything the HIP library produced.
+
+    python tests/golden/make_converged.py lens16          # 275 x 275 x 315 zone plate
+    python tests/golden/make_converged.py lens16_grad     # the same with its design slab
+    python tests/golden/make_converged.py sphere64_fd     # 64^3 finite-difference gradient
+
+lens16       The 16 um zone plate of the Fig. 1 benchmark (275 x 275 x 315 at
+             lambda/16): the FP64 CBS iteration run until eta <= 1e-9, which the
+             converged field E_s* = A^-1 S (unique, independent of the shift)
+             then matches to about eta / (1 - rho).  Stored: the scattered field
+             on the focal plane z = z0 and on the xz plane through the axis, at
+             4096 voxels drawn with default_rng(7), and the whole-volume norm.
+lens16_grad  The same lens with its seed-0 design slab (the adjoint-gradient
+             case, objective |E(r0)|^2; objective and optimisation paragraphs):
+             forward and adjoint solves to eta <= 1e-9, the gradient
+             2 k0^2 Re(E_adj . E) over the slab at 4096 slab voxels
+             (default_rng(8)), on the slab's middle plane, and its norm.
+sphere64_fd  The 64^3 sphere at lambda/6 with a 6-voxel seeded design slab: the
+             adjoint gradient and FP64 central differences (h = 1e-3, solves
+             warm-started from the base field to eta <= 1e-12) at 32 slab voxels
+             drawn without replacement with default_rng(1).
+
+Long solves run in chunks of 50 iterations (each chunk continues exactly where
+the previous stopped: the iteration depends only on the current field) and
+write a checkpoint to the directory named by --ckpt, so an interrupted run
+resumes.
+"""
+
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+from oracle import cbs as oc  # noqa: E402
+from paper_2506_15411_amd import scenes  # noqa: E402
+
+TOL = 1e-9
+CHUNK = 50
+
+
+def log(*a):
+    print(time.strftime("%H:%M:%S"), *a, flush=True)
+
+
+def converge(g, eps, S, tag, ckpt_dir, tol=TOL, max_iter=20000):
+    """FP64 CBS from E_s = 0 until eta <= tol, in resumable chunks."""
+    path = os.path.join(ckpt_dir, f"{tag}.npz") if ckpt_dir else None
+    E, done, hist = None, 0, []
+    if path and os.path.exists(path):
+        z = np.load(path)
+        E, done, hist = z["E"], int(z["iterations"]), list(z["history"])
+        log(f"{tag}: resuming at iteration {done}, eta {hist[-1]:.3e}")
+    eta = hist[-1] if hist else math.inf
+    while eta > tol and done < max_iter:
+        res = oc.cbs(g, eps, S, tol=tol, max_iter=min(CHUNK, max_iter - done), E0=E)
+        E, done, eta = res.E_s, done + res.iterations, res.eta
+        hist += res.history
+        log(f"{tag}: iteration {done}, eta {eta:.3e}")
+        if path:
+            np.savez(path + ".tmp.npz", E=E, iterations=done, history=np.array(hist))
+            os.replace(path + ".tmp.npz", path)
+    if eta > tol:
+        raise RuntimeError(f"{tag}: eta {eta:.3e} > {tol} after {done} iterations")
+    return E, done, np.array(hist)
+
+
+def lens16(ckpt):
+    sc = scenes.zoneplate16()
+    g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
+    oc.validate(g, sc.eps_r)
+    E, its, hist = converge(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), "lens16_fwd", ckpt)
+    nx, ny, nz = sc.shape
+    x0, y0, z0 = sc.r0
+    rng = np.random.default_rng(7)
+    vz, vy, vx = rng.integers(0, nz, 4096), rng.integers(0, ny, 4096), rng.integers(0, nx, 4096)
+    out = os.path.join(HERE, "lens16_converged.npz")
+    np.savez_compressed(
+        out, shape=np.array(sc.shape), r0=np.array(sc.r0), tol=TOL, iterations=its,
+        eta=hist[-1], eps_shift=oc.potentials(g, sc.eps_r).eps,
+        focal_plane=E[:, z0].astype(np.complex64),          # [3, ny, nx] at z = z0
+        xz_plane=E[:, :, y0, :].astype(np.complex64),       # [3, nz, nx] at y = y0
+        vox=np.stack([vx, vy, vz]), vox_E=E[:, vz, vy, vx],  # complex128 [3, 4096]
+        norm=float(np.sqrt(np.sum(np.abs(E) ** 2))))
+    log(f"wrote {out}: {its} iterations, eta {hist[-1]:.3e}")
+
+
+def lens16_grad(ckpt):
+    sc = scenes.zoneplate16_design(0)
+    g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
+    oc.validate(g, sc.eps_r)
+    Es, it1, h1 = converge(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), "lens16d_fwd", ckpt)
+    E = oc.plane_wave(g) + Es
+    del Es
+    src = oc.adjoint_point_source(g, E, sc.r0)
+    Ea, it2, h2 = converge(g, sc.eps_r, src, "lens16d_adj", ckpt)
+    lo, hi = sc.design_box
+    grad = oc.gradient(g, E, Ea, lo, hi, scale=2.0)          # [bz, by, bx]
+    bz, by, bx = grad.shape
+    rng = np.random.default_rng(8)
+    vz, vy, vx = rng.integers(0, bz, 4096), rng.integers(0, by, 4096), rng.integers(0, bx, 4096)
+    out = os.path.join(HERE, "lens16_gradient_converged.npz")
+    np.savez_compressed(
+        out, shape=np.array(sc.shape), r0=np.array(sc.r0), box_lo=np.array(lo),
+        box_hi=np.array(hi), tol=TOL, iterations=np.array([it1, it2]),
+        eta=np.array([h1[-1], h2[-1]]), objective=oc.focal_objective(E, sc.r0),
+        vox=np.stack([vx, vy, vz]), vox_grad=grad[vz, vy, vx],
+        mid_plane=grad[bz // 2].astype(np.float32), norm=float(np.linalg.norm(grad)))
+    log(f"wrote {out}: iterations {it1} + {it2}")
+
+
+def sphere64_slab():
+    """The 64^3 gradient case: the sphere scene with a 6-voxel slab of seeded
+    random permittivity below it (z in [18, 24), x, y in [8, 56)), objective
+    |E(r0)|^2 at r0 = (32, 32, 44)."""
+    sc = scenes.sphere64()
+    eps = sc.eps_r.copy()
+    rng = np.random.default_rng(0)
+    sl = (slice(18, 24), slice(8, 56), slice(8, 56))
+    eps[sl] = np.clip(eps[sl] + rng.uniform(-0.25, 0.25, eps[sl].shape), 1.0, 2.1).astype(np.float32)
+    return sc, eps, (32, 32, 44), (8, 8, 18), (56, 56, 24)
+
+
+def sphere64_fd(ckpt):
+    sc, eps32, r0, lo, hi = sphere64_slab()
+    g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
+    eps = eps32.astype(np.float64)
+    tol = 1e-12
+    L0, res = oc.objective_of_eps(g, eps, r0, tol, 40000)
+    E = oc.plane_wave(g) + res.E_s
+    adj = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, E, r0), tol=tol, max_iter=40000)
+    grad = oc.gradient(g, E, adj.E_s, lo, hi, scale=2.0)
+    bz, by, bx = grad.shape
+    pick = np.random.default_rng(1).choice(bz * by * bx, size=32, replace=False)
+    h = 1e-3
+    vox, fd, ga = [], [], []
+    for n, v in enumerate(pick):
+        zi, yi, xi = v // (by * bx), (v // bx) % by, v % bx
+        x, y, z = lo[0] + xi, lo[1] + yi, lo[2] + zi
+        ep, em = eps.copy(), eps.copy()
+        ep[z, y, x] += h
+        em[z, y, x] -= h
+        Lp, rp = oc.objective_of_eps(g, ep, r0, tol, 40000, res.E_s)
+        Lm, rm = oc.objective_of_eps(g, em, r0, tol, 40000, res.E_s)
+        vox.append((x, y, z))
+        fd.append((Lp - Lm) / (2 * h))
+        ga.append(grad[zi, yi, xi])
+        log(f"sphere64_fd {n + 1}/32: voxel {vox[-1]} fd {fd[-1]:.9e} adjoint {ga[-1]:.9e} "
+            f"({rp.iterations} + {rm.iterations} iterations)")
+    out = os.path.join(HERE, "sphere64_fd_gradient.npz")
+    np.savez_compressed(out, r0=np.array(r0), box_lo=np.array(lo), box_hi=np.array(hi), h=h,
+                        tol=tol, objective=L0, vox=np.array(vox), fd=np.array(fd),
+                        adjoint=np.array(ga), grad_norm=float(np.linalg.norm(grad)),
+                        grad_max=float(np.abs(grad).max()))
+    log(f"wrote {out}")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("which", choices=["lens16", "lens16_grad", "sphere64_fd"], nargs="+")
+    ap.add_argument("--ckpt", default=None, help="directory for resumable checkpoints")
+    a = ap.parse_args(argv)
+    if a.ckpt:
+        os.makedirs(a.ckpt, exist_ok=True)
+    for w in a.which:
+        {"lens16": lens16, "lens16_grad": lens16_grad, "sphere64_fd": sphere64_fd}[w](a.ckpt)
+
+
+if __name__ == "__main__":
+    main()

@@ -3,10 +3,13 @@ benchmark times (the same plans and kernels; only the inputs differ).
 
 * 621 x 621 x 261 (the design volume): a uniform lossy medium driven by a few
   single Fourier modes, whose every iterate has a closed form (checked at all
-  voxels of sampled x, y and z lines and at random voxels), and two full CBS
-  iterations of the 100 um lens against the FP64 oracle over the whole volume.
-* 275 x 275 x 315 (the 16 um lens): equal-iteration parity with the oracle of
-  the forward field, and of the design-slab gradient (forward + adjoint).
+  voxels of sampled x, y and z lines and at random voxels), and twenty CBS
+  iterations of the 100 um lens with its design slab (the benchmarked medium)
+  against the FP64 oracle over the whole volume.
+* 275 x 275 x 315 (the 16 um lens): a hundred iterations of the forward field
+  against the oracle, and twenty forward + twenty adjoint iterations of the
+  design-slab gradient.  The converged field and gradient are checked in
+  test_gpu_converged.py.
 * 189 x 189 x 121 (the 32 um kinoform of the optimisation benchmark):
   equal-iteration parity of the forward field.
 * The served grids (128^3, 192 x 192 x 256): one Green's-operator application.
@@ -98,27 +101,37 @@ def test_design_volume_single_modes_closed_form(device):
     p.close()
 
 
-def test_design_volume_lens_two_iterations_vs_oracle(device):
+def test_design_volume_lens_twenty_iterations_vs_oracle(device):
+    """The benchmarked volume and medium (100 um lens with its design slab):
+    20 CBS iterations on the GPU and in the FP64 oracle, whole volume."""
     sc = scenes.zoneplate100_design(0)
+    k = 20
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
-    E, st = p.solve(tol=0.0, max_iter=2, scattered=True)
+    E, st = p.solve(tol=0.0, max_iter=k, scattered=True, history=True)
+    hist = np.array(p.history())
     g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
-    res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=2)
-    assert abs(st.residual - res.eta) < 1e-4 * res.eta
-    assert rel_chunked(E, res.E_s) < 1e-4
+    res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=k)
+    err = rel_chunked(E, res.E_s)
+    print(f"621x621x261, {k} iterations: rel-L2 {err:.2e}, eta {st.residual:.4e} vs {res.eta:.4e}")
+    assert st.iterations == k
+    assert np.all(np.abs(hist - np.array(res.history)) <= 1e-4 * np.array(res.history))
+    assert err < 1e-4
     p.close()
 
 
-def test_lens16_equal_iterations_vs_oracle(device):
-    sc = scenes.zoneplate16_design(0)
+def test_lens16_hundred_iterations_vs_oracle(device):
+    """The 16 um lens of the Fig. 1 benchmark: 100 iterations, whole volume."""
+    sc = scenes.zoneplate16()
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
-    k = 6
+    k = 100
     E, st = p.solve(tol=0.0, max_iter=k, scattered=True)
     g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
     res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=k)
-    assert rel_chunked(E, res.E_s) < 1e-4
+    err = rel_chunked(E, res.E_s)
+    print(f"275x275x315, {k} iterations: rel-L2 {err:.2e}")
+    assert err < 1e-4
     p.close()
 
 
@@ -128,7 +141,7 @@ def test_lens16_gradient_equal_iterations_vs_oracle(device):
     iterate, k adjoint iterations, the gradient over the 2 um slab; the oracle
     does the same in FP64."""
     sc = scenes.zoneplate16_design(0)
-    k = 6
+    k = 20
     lo, hi = sc.design_box
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
@@ -143,7 +156,9 @@ def test_lens16_gradient_equal_iterations_vs_oracle(device):
     ga = oc.solve_adjoint(g, sc.eps_r, oc.adjoint_point_source(g, Eo, sc.r0), tol=0.0, max_iter=k)
     gref = oc.gradient(g, Eo, ga.E_s, lo, hi, scale=2.0)
     assert grad.shape == gref.shape
-    assert np.linalg.norm(grad - gref) / np.linalg.norm(gref) < 1e-3
+    err = np.linalg.norm(grad - gref) / np.linalg.norm(gref)
+    print(f"275x275x315 slab gradient after {k} + {k} iterations: rel-L2 {err:.2e}")
+    assert err < 1e-4
 
 
 def test_lens32_kinoform_equal_iterations_vs_oracle(device):

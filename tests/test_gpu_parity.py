@@ -87,6 +87,7 @@ def test_sphere64_equal_iterations_and_converged(device):
     Eo, res = oc.solve_forward(g, sc.eps_r, tol=0.0, max_iter=20)
     assert rel(E.cpu().numpy(), Eo) < 1e-4
     E, st = p.solve(tol=1e-6, max_iter=5000, check_every=10, history=True)
+    assert st.status == L.CBS_OK and st.converged and st.residual <= 1e-6
     Eo, res = oc.solve_forward(g, sc.eps_r, tol=1e-9, max_iter=20000)
     print(f"sphere64: gpu {st.iterations} it (eta {st.residual:.2e}), oracle {res.iterations} it")
     assert rel(E.cpu().numpy(), Eo) < 1e-3

@@ -512,3 +512,73 @@ def test_cbs_sphere_field_approaches_mie():
     e10 = err(107, LAM / 10, (13, 13, 27))
     assert e6 < 0.15
     assert e10 < 0.8 * e6
+
+
+# ---------------------------------------------------------------------------
+# Admissibility checks (validate): the conditions under which the CBS of
+# reference [25] converges and the scattered-field formulation holds
+# ---------------------------------------------------------------------------
+def _layer_mask_bruteforce(shape, pml):
+    nx, ny, nz = shape
+    m = np.zeros((nz, ny, nx), dtype=bool)
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                m[k, j, i] = (i < pml[0] or i >= nx - pml[0] or j < pml[1] or j >= ny - pml[1]
+                              or k < pml[2] or k >= nz - pml[2])
+    return m
+
+
+def test_validate_admits_passive_media_and_rejects_the_rest():
+    shape, pml = (7, 6, 9), (2, 1, 3)
+    nbg = 1.33
+    g = oc.Grid(*shape, LAM / 6, LAM, nbg, pml)
+    layer = _layer_mask_bruteforce(shape, pml)
+    assert np.array_equal(~oc.interior_mask(g), layer)
+    nb2 = np.float32(nbg * nbg)
+    base = np.full(g.vshape, nb2, dtype=np.float32)
+    oc.validate(g, base)                                   # homogeneous background
+    # lossless and lossy material anywhere in the interior, including the
+    # voxels next to every face of the layer
+    inner = np.argwhere(~layer)
+    for z, y, x in inner:
+        e = base.astype(np.complex64)
+        e[z, y, x] = 2.1 + (0.0 if (x + y + z) % 2 else 0.3j)
+        oc.validate(g, e)
+    # any material inside the layer is rejected, on each of its voxels
+    for z, y, x in np.argwhere(layer):
+        e = base.copy()
+        e[z, y, x] = 2.1
+        with pytest.raises(ValueError, match="absorbing layer"):
+            oc.validate(g, e)
+    # absorption inside the layer is material too
+    e = base.astype(np.complex64)
+    e[0, 0, 0] = nb2 + 0.01j
+    with pytest.raises(ValueError, match="absorbing layer"):
+        oc.validate(g, e)
+    # gain (Im eps_r < 0), however small, is not passive
+    z, y, x = inner[len(inner) // 2]
+    e = base.astype(np.complex64)
+    e[z, y, x] = 2.0 - 1e-6j
+    with pytest.raises(ValueError, match="gain"):
+        oc.validate(g, e)
+    # non-finite values
+    for bad in (np.nan, np.inf, -np.inf):
+        e = base.copy()
+        e[z, y, x] = bad
+        with pytest.raises(ValueError, match="non-finite"):
+            oc.validate(g, e)
+    e = base.astype(np.complex64)
+    e[z, y, x] = complex(1.5, np.nan)
+    with pytest.raises(ValueError, match="non-finite"):
+        oc.validate(g, e)
+    # the volume must be [nz, ny, nx]
+    with pytest.raises(ValueError, match="shape"):
+        oc.validate(g, np.full(shape, nb2, dtype=np.float32))
+    # a background value not representable in float32 is compared at float32
+    oc.validate(g, np.full(g.vshape, np.float32(nbg * nbg), dtype=np.complex64))
+    # no layer: material may reach the grid edge
+    g0 = oc.Grid(*shape, LAM / 6, LAM, nbg, (0, 0, 0))
+    e = base.copy()
+    e[0, 0, 0] = 2.1
+    oc.validate(g0, e)
