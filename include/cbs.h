@@ -56,7 +56,7 @@ enum { CBS_F32 = 0, CBS_C64 = 1 };   /* permittivity dtype */
 
 enum {
   CBS_SRC_NONE = 0,        /* S = 0 */
-  CBS_SRC_PLANE_WAVE = 1,  /* S = k0^2 (eps_r - n_bg^2) pol exp(i kb z), +z incidence  */
+  CBS_SRC_PLANE_WAVE = 1,  /* S = k0^2 (eps_r - n_bg^2) pol exp(i k.r), k towards +z     */
   CBS_SRC_FIELD = 2,       /* S = field (device complex64 [3][nz][ny][nx], units 1/m^2) */
   CBS_SRC_POINT = 3,       /* S = amp at voxel r0, zero elsewhere (units 1/m^2)        */
   CBS_SRC_FIELD_CONJ = 4   /* S = conj(field), field as for FIELD: the adjoint source
@@ -92,10 +92,16 @@ typedef struct {
 typedef struct {
   int kind;                 /* CBS_SRC_*                                              */
   double pol[3][2];         /* PLANE_WAVE: polarisation (re, im) per component;
-                               all zero means x-polarised                             */
+                               all zero means x-polarised (the design paragraph's
+                               illumination); the caller keeps it transverse to k    */
   const void* field;        /* FIELD, FIELD_CONJ: device complex64 [3][nz][ny][nx]    */
   int r0[3];                /* POINT: voxel (ix, iy, iz)                              */
   double amp[3][2];         /* POINT: amplitude (re, im) per component                */
+  double dir[2];            /* PLANE_WAVE: transverse direction cosines (sx, sy) =
+                               (kx, ky) / kb with sx^2 + sy^2 < 1, kz = kb sqrt(1 -
+                               sx^2 - sy^2) > 0; (0, 0) is normal incidence.  The
+                               incident wave is pol exp(i k.r), phase 0 at voxel
+                               (0, 0, 0).  Zero-initialise for normal incidence.     */
 } cbs_source;
 
 /* Device bytes a plan of this grid needs as workspace (exact). 0 if the grid
@@ -190,6 +196,34 @@ int cbs_solve_poll(cbs_plan_t plan, int* done, int* outstanding);
  * complete when the plan's stream reaches this point. */
 int cbs_solve_end(cbs_plan_t plan, cbs_stats* stats);
 
+/* ---- batched illuminations -----------------------------------------------
+ * Several plane-wave illuminations of one medium solved together (multi-angle
+ * or multi-polarisation illumination; the paper's design uses one x-polarised
+ * normal-incidence wave, design paragraph).  One launch of each pass advances
+ * all of them: the potential is read once per row for all illuminations and
+ * small grids need a fraction of the launches.  Every illumination has its own
+ * residual; the solve stops when the largest reaches tol (or at max_iter), so
+ * all illuminations run the same number of iterations, and at equal iteration
+ * counts each field is bit-identical to a cbs_solve of that source alone.
+ *
+ * Device bytes of the batch workspace for `count` illuminations (1..8): the
+ * spectral work fields, residual partials and phase tables of the batch; 0 if
+ * the grid is not supported or count is out of range. */
+size_t cbs_batch_workspace_bytes(int nx, int ny, int nz, int count);
+
+/* Solve `count` (1..8) PLANE_WAVE sources srcs[0..count) on the plan's medium.
+ *   E_dev      complex64 [count][3][nz][ny][nx]: total fields (scattered with
+ *              CBS_RETURN_SCATTERED); with CBS_WARM_START it holds initial
+ *              iterates (total fields)
+ *   stats      count entries: the shared iteration count, each illumination's
+ *              last residual and whether it is <= tol
+ *   work_dev   device memory of >= cbs_batch_workspace_bytes, 256-byte aligned,
+ *              owned by the caller (the plan's own spectral field is not used)
+ * Returns CBS_OK when every illumination met tol, CBS_NOT_CONVERGED at max_iter,
+ * or an error.  Synchronises the plan's stream. */
+int cbs_solve_batch(cbs_plan_t plan, int count, const cbs_source* srcs, void* E_dev,
+                    const cbs_opts* opts, cbs_stats* stats, void* work_dev, size_t work_bytes);
+
 /* Grouped step: enqueue `iters` iterations on every plan (each on its own
  * stream, so their work overlaps), then wait for all of them; done_out[i] = 1
  * for plans whose solve has stopped.  Every plan must have a solve begun. */
@@ -235,6 +269,24 @@ typedef struct {
  * Synchronises the plan's stream.  Uses the plan's workspace. */
 int cbs_lens_metrics(cbs_plan_t plan, const void* E_dev, const int lo[3], const int hi[3],
                      double disc_factor, double aperture_m, double e0, cbs_lens_figures* out);
+
+/* Total-field / scattered-field source of a plane wave (PLANE_WAVE src: pol
+ * and direction; NULL = x-polarised normal incidence) for the box [lo, hi)
+ * (x, y, z, half-open, inside the grid):
+ *     S = (L - K_bg)(chi E_inc),  K_bg = kb^2 (1 + i sigma),
+ * chi the box's indicator.  Used as the FIELD source of cbs_solve it injects
+ * the plane wave on the box's faces: in the background medium the solution is
+ * exactly chi E_inc, and with material inside the box it is the total field
+ * inside the box and the scattered field outside (an alternative to the
+ * volume source of the scattered-field formulation, for a lens illuminated
+ * through its aperture; the paper's own solves use the plane wave of the
+ * design paragraph).  Every term of L(chi E_inc) is a product of 1D spectral
+ * derivatives of the box's edges, formed in FP64 (direct O(n^2) sums per axis)
+ * and rounded to complex64 in S_dev [3][nz][ny][nx] (1/m^2).  Uses the plan's
+ * spectral work field as scratch (CBS_E_STATE while a solve is in progress);
+ * needs no permittivity.  Asynchronous on the plan's stream. */
+int cbs_tfsf_source(cbs_plan_t plan, const cbs_source* src, const int lo[3], const int hi[3],
+                    void* S_dev);
 
 /* One application of the Green's operator of the current medium:
  * out = F^-1 G^(p) F in  (complex64 fields; in and out may not alias).

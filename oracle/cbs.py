@@ -274,21 +274,56 @@ def curl_curl_apply(g: Grid, E: np.ndarray) -> np.ndarray:
 # Sources (design paragraph: x-polarised plane wave, normal incidence;
 # Fig. 2 caption and optimisation paragraph: adjoint source at r0)
 # ---------------------------------------------------------------------------
-def plane_wave(g: Grid, pol=(1.0, 0.0, 0.0)) -> np.ndarray:
-    """E_inc = pol * exp(i kb z), z = k d, phase 0 at k = 0, along +z."""
-    z = np.arange(g.nz) * g.pitch
-    ph = np.exp(1j * g.kb * z)
+def wave_vector(g: Grid, direction=(0.0, 0.0)):
+    """(kx, ky, kz) of a plane wave travelling towards +z with transverse
+    direction cosines direction = (kx/kb, ky/kb); (0, 0) is normal incidence."""
+    sx, sy = (float(v) for v in direction)
+    c2 = 1.0 - sx * sx - sy * sy
+    if not c2 > 0.0:
+        raise ValueError("direction cosines must satisfy sx^2 + sy^2 < 1")
+    return g.kb * sx, g.kb * sy, g.kb * math.sqrt(c2)
+
+
+def plane_wave(g: Grid, pol=(1.0, 0.0, 0.0), direction=(0.0, 0.0)) -> np.ndarray:
+    """E_inc = pol * exp(i k.r), r = (i, j, k) d, phase 0 at the voxel (0, 0, 0),
+    k from ``wave_vector`` (normal incidence: exp(i kb z) along +z)."""
+    kx, ky, kz = wave_vector(g, direction)
+    ph = (np.exp(1j * kz * np.arange(g.nz) * g.pitch)[:, None, None]
+          * np.exp(1j * ky * np.arange(g.ny) * g.pitch)[None, :, None]
+          * np.exp(1j * kx * np.arange(g.nx) * g.pitch)[None, None, :])
     E = np.zeros((3,) + g.vshape, dtype=np.complex128)
     for c in range(3):
         if pol[c] != 0:
-            E[c] = complex(pol[c]) * ph[:, None, None]
+            E[c] = complex(pol[c]) * ph
     return E
 
 
-def plane_wave_source(g: Grid, eps_r: np.ndarray, pol=(1.0, 0.0, 0.0)) -> np.ndarray:
+def plane_wave_source(g: Grid, eps_r: np.ndarray, pol=(1.0, 0.0, 0.0),
+                      direction=(0.0, 0.0)) -> np.ndarray:
     """Scattered-field source S = k0^2 (eps_r - n_bg^2) E_inc."""
     contrast = g.k0 ** 2 * (np.asarray(eps_r).astype(np.complex128) - g.n_bg ** 2)
-    return contrast[None] * plane_wave(g, pol)
+    return contrast[None] * plane_wave(g, pol, direction)
+
+
+def box_mask(g: Grid, lo, hi) -> np.ndarray:
+    """Indicator of the half-open voxel box [lo, hi) (x, y, z) over [nz, ny, nx]."""
+    m = np.zeros(g.vshape, dtype=bool)
+    m[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+    return m
+
+
+def tfsf_source(g: Grid, lo, hi, pol=(1.0, 0.0, 0.0), direction=(0.0, 0.0)) -> np.ndarray:
+    """Total-field / scattered-field source of a plane wave for the box [lo, hi):
+    S = (L - K_bg)(chi E_inc),  K_bg = kb^2 + i kb^2 sigma,  chi the box indicator.
+
+    In the background medium (L - K_bg) E = S is solved exactly by E = chi E_inc:
+    the incident wave inside the box and nothing outside.  With material inside
+    the box, E - chi E_inc solves the scattered-field problem, so the solution
+    is the total field inside the box and the scattered field outside.  L is the
+    same spectral curl-curl as the solver's operator (``curl_curl_apply``)."""
+    U = box_mask(g, lo, hi)[None] * plane_wave(g, pol, direction)
+    Kbg = g.kb ** 2 * (1.0 + 1j * absorber_sigma(g))
+    return curl_curl_apply(g, U) - Kbg[None] * U
 
 
 def point_source(g: Grid, r0, amp) -> np.ndarray:
@@ -345,14 +380,14 @@ def cbs(g: Grid, eps_r: np.ndarray, S: np.ndarray, tol: float = 1e-6,
 
 
 def solve_forward(g: Grid, eps_r: np.ndarray, tol: float = 1e-6, max_iter: int = 20000,
-                  pol=(1.0, 0.0, 0.0), eps_shift: float | None = None):
+                  pol=(1.0, 0.0, 0.0), eps_shift: float | None = None, direction=(0.0, 0.0)):
     """Total field E = E_inc + E_s for plane-wave illumination.
 
     Returns (E_total, CBSResult)."""
     validate(g, eps_r)
-    S = plane_wave_source(g, eps_r, pol)
+    S = plane_wave_source(g, eps_r, pol, direction)
     res = cbs(g, eps_r, S, tol, max_iter, eps_shift=eps_shift)
-    return plane_wave(g, pol) + res.E_s, res
+    return plane_wave(g, pol, direction) + res.E_s, res
 
 
 # ---------------------------------------------------------------------------

@@ -107,3 +107,44 @@ def gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: float = 
     if info != 0:
         raise RuntimeError(f"GMRES did not converge (info={info})")
     return x.reshape(shp)
+
+
+def cbs_gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: float = 1e-10,
+                    restart: int = 20, maxiter: int = 2000, x0: np.ndarray | None = None,
+                    callback=None) -> np.ndarray:
+    """E_s = A^-1 S by FP64 GMRES on the preconditioned system of the CBS
+    iteration (references [25], [26]).  The CBS step E <- E + gamma (G (V E + S) - E)
+    has the fixed point of
+
+        gamma (I - G V) E = gamma G S,
+
+    which is A E = S multiplied by gamma G (G = (L - kb^2 - i eps)^-1, V = K -
+    kb^2 - i eps, so (L - kb^2 - i eps)(I - G V) = L - K = A); GMRES on it reaches
+    the same solution as the iteration without its slow tail.  rtol is the
+    relative residual of this preconditioned system; x0 is an initial E_s (for
+    instance a CBS iterate).  callback(k, residual) is called every inner step."""
+    pot = _cbs.potentials(g, eps_r)
+    shp = (3,) + g.vshape
+    N3 = 3 * g.n_vox
+    gam = pot.gamma[None]
+    V = pot.V[None]
+
+    def mv(v):
+        E = np.asarray(v).reshape(shp)
+        return (gam * (E - _cbs.green_apply(g, V * E, pot.kt2))).reshape(-1)
+
+    M = spla.LinearOperator((N3, N3), matvec=mv, dtype=np.complex128)
+    b = (gam * _cbs.green_apply(g, np.asarray(S, dtype=np.complex128), pot.kt2)).reshape(-1)
+    steps = [0]
+
+    def cb(r):
+        steps[0] += 1
+        if callback is not None:
+            callback(steps[0], float(r))
+
+    x, info = spla.gmres(M, b, x0=None if x0 is None else np.asarray(x0).reshape(-1),
+                         rtol=rtol, atol=0.0, restart=restart, maxiter=maxiter,
+                         callback=cb, callback_type="pr_norm")
+    if info != 0:
+        raise RuntimeError(f"GMRES did not converge (info={info})")
+    return x.reshape(shp)

@@ -182,30 +182,58 @@ __global__ void k_point_amp(DevState* st, const float2* E, long long idx, long l
 // a separate launch when the x-pass does not fold it in
 constexpr int kResThreads = 256;
 __global__ void __launch_bounds__(kResThreads)
-k_residual(const double* part, int nb, DevState* st, double* hist) {
+k_residual(const double* part, int per_b, int nb, DevState* st, double* hist) {
   __shared__ double red[2 * kResStreams];
   if (st->done || !st->pending) return;
-  residual_finish<kResThreads>(part, nb, st, hist, red);
+  residual_finish<kResThreads>(part, per_b, nb, st, hist, red);
   if (threadIdx.x == 0) st->pending = 0;
 }
 
-// E += sign * pol exp(i kb z)  (incident field)
-__global__ void k_incident(float2* E, const float2* phase, int nx, int ny, int nz, float2 p0,
-                           float2 p1, float2 p2, float sign) {
-  const long long N = (long long)nx * ny * nz;
+// E_b += sign * pol_b exp(i k_b . r) for every illumination b of a solve
+// (the incident plane waves; normal incidence: pol exp(i kb z))
+__global__ void k_incident(CbsArgs a, float sign) {
+  const long long N = (long long)a.nx * a.ny * a.nz;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
-    const int z = (int)(i / ((long long)nx * ny));
-    const float2 ph = phase[z];
-    const float2 pc[3] = {p0, p1, p2};
+    const int x = (int)(i % a.nx);
+    const int y = (int)((i / a.nx) % a.ny);
+    const int z = (int)(i / ((long long)a.nx * a.ny));
+    for (int b = 0; b < a.nb; ++b) {
+      float2 ph = a.phase[b * a.nz + z];
+      if (a.oblique) ph = cmul(cmul(ph, a.phy[b * a.ny + y]), a.phx[b * a.nx + x]);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const float2 inc = cmul(ph, pc[c]);
-      float2 e = E[c * N + i];
-      e.x += sign * inc.x;
-      e.y += sign * inc.y;
-      E[c * N + i] = e;
+      for (int c = 0; c < 3; ++c) {
+        const float2 inc = cmul(ph, a.pol[b][c]);
+        float2* ep = a.E + b * a.sEb + c * a.sE + i;
+        float2 e = *ep;
+        e.x += sign * inc.x;
+        e.y += sign * inc.y;
+        *ep = e;
+      }
     }
+  }
+}
+
+// Plane-wave phase tables of the illuminations of a solve, in FP64 rounded to
+// FP32: phx[b][x] = exp(i kx_b d x), phy[b][y] = exp(i ky_b d y),
+// phz[b][z] = exp(i kz_b d z); phase zero at the voxel (0, 0, 0).
+struct Kvec {
+  int nb;
+  double kd[kMaxIllum][3];   // (kx, ky, kz) d of each illumination
+};
+__global__ void k_phase_tables(float2* phx, float2* phy, float2* phz, int nx, int ny, int nz,
+                               Kvec kv) {
+  const int per = nx + ny + nz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kv.nb * per; i += gridDim.x * blockDim.x) {
+    const int b = i / per, j = i - b * per;
+    int axis, k;
+    float2* out;
+    if (j < nx) { axis = 0; k = j; out = phx + b * nx + k; }
+    else if (j < nx + ny) { axis = 1; k = j - nx; out = phy + b * ny + k; }
+    else { axis = 2; k = j - nx - ny; out = phz + b * nz + k; }
+    double sn, cs;
+    sincos(kv.kd[b][axis] * (double)k, &sn, &cs);
+    *out = make_float2((float)cs, (float)sn);
   }
 }
 
@@ -391,6 +419,157 @@ k_disc_flux(const double2* ex, const double2* ey, const double2* hx, const doubl
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
+// ---------------------------------------------------------------------------
+// total-field / scattered-field source: S = (L - K_bg)(chi E_inc)
+// ---------------------------------------------------------------------------
+// chi is the indicator of a box and E_inc = q exp(i k.r), so chi E_inc = q u
+// with u = fx(x) fy(y) fz(z), f_a(i) = chi_a(i) exp(i k_a d i), and every term
+// of L (q u) = F^-1 [ |p|^2 q u^ - pt (pt . q) u^ ] is a product of 1D
+// transforms of the f_a.  Per axis the tables hold (FP64, n_a entries each,
+// axes one after the other):
+//   tab[0] = f,  tab[1] = F f (spectrum),  tab[2] = F^-1[p^2 F f],
+//   tab[3] = F^-1[pt F f],  tab[4] = F^-1[pt^2 F f]   (p in 1/m; pt = p except
+// 0 at the Nyquist bin of an even axis), by direct O(n^2) sums.
+struct TfsfArgs {
+  int n[3], lo[3], hi[3], off[3];   // axis lengths, box, table offsets
+  int ntot;                         // n[0] + n[1] + n[2]
+  double kd[3];                     // (kx, ky, kz) d of the plane wave
+  double pitch;
+  double2* tab;                     // 5 ntot entries
+};
+
+__device__ __forceinline__ int tfsf_axis(const TfsfArgs& t, int j, int& i) {
+  const int a = j < t.n[0] ? 0 : (j < t.n[0] + t.n[1] ? 1 : 2);
+  i = j - t.off[a];
+  return a;
+}
+
+// f and its DFT (one thread per axis entry)
+__global__ void k_tfsf_forward(TfsfArgs t) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < t.ntot; j += gridDim.x * blockDim.x) {
+    int m;
+    const int a = tfsf_axis(t, j, m);
+    const int n = t.n[a];
+    double re = 0.0, im = 0.0;
+    for (int i = t.lo[a]; i < t.hi[a]; ++i) {   // f vanishes outside the box
+      double sf, cf, sw, cw;
+      sincos(t.kd[a] * (double)i, &sf, &cf);
+      sincos(-2.0 * M_PI * (double)(((long long)m * i) % n) / (double)n, &sw, &cw);
+      re += cf * cw - sf * sw;
+      im += cf * sw + sf * cw;
+    }
+    t.tab[t.ntot + j] = make_double2(re, im);
+    double sf = 0.0, cf = 0.0;
+    if (m >= t.lo[a] && m < t.hi[a]) sincos(t.kd[a] * (double)m, &sf, &cf);
+    t.tab[j] = make_double2(cf, sf);
+  }
+}
+
+// the three filtered inverse transforms (one thread per axis entry)
+__global__ void k_tfsf_inverse(TfsfArgs t) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < t.ntot; j += gridDim.x * blockDim.x) {
+    int i;
+    const int a = tfsf_axis(t, j, i);
+    const int n = t.n[a];
+    double r2 = 0.0, i2 = 0.0, r1 = 0.0, i1 = 0.0, rt = 0.0, it = 0.0;
+    for (int m = 0; m < n; ++m) {
+      const double2 F = t.tab[t.ntot + t.off[a] + m];
+      const int mm = (m < (n + 1) / 2) ? m : m - n;
+      const double pm = 2.0 * M_PI * (double)mm / ((double)n * t.pitch);
+      const double ptm = ((n & 1) == 0 && 2 * m == n) ? 0.0 : pm;
+      double sw, cw;
+      sincos(2.0 * M_PI * (double)(((long long)m * i) % n) / (double)n, &sw, &cw);
+      const double gr = F.x * cw - F.y * sw, gi = F.x * sw + F.y * cw;   // F(m) e^{+2 pi i m i/n}
+      r2 += pm * pm * gr;
+      i2 += pm * pm * gi;
+      r1 += ptm * gr;
+      i1 += ptm * gi;
+      rt += ptm * ptm * gr;
+      it += ptm * ptm * gi;
+    }
+    const double inv = 1.0 / (double)n;
+    t.tab[2 * t.ntot + j] = make_double2(r2 * inv, i2 * inv);
+    t.tab[3 * t.ntot + j] = make_double2(r1 * inv, i1 * inv);
+    t.tab[4 * t.ntot + j] = make_double2(rt * inv, it * inv);
+  }
+}
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zmul3(double2 a, double2 b, double2 c) {
+  return zmul(zmul(a, b), c);
+}
+
+struct TfsfAssemble {
+  TfsfArgs t;
+  int nx, ny, nz, px, py, pz, order;
+  double sigma_max, kb2;
+  double2 q[3];          // polarisation
+  float2* S;             // [3][nz][ny][nx]
+};
+
+// S_c = q_c (D2x fy fz + fx D2y fz + fx fy D2z - kb^2 (1 + i sigma) u)
+//       - sum_b q_b T_c T_b u   (T_c T_b u = (T1 f)(T1 f)(f) for c != b, (T2 f)(f)(f) for c = b)
+__global__ void k_tfsf_assemble(TfsfAssemble A) {
+  const TfsfArgs& t = A.t;
+  const long long N = (long long)A.nx * A.ny * A.nz;
+  const double2* f = t.tab;
+  const double2* d2 = t.tab + 2 * t.ntot;
+  const double2* t1 = t.tab + 3 * t.ntot;
+  const double2* t2 = t.tab + 4 * t.ntot;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % A.nx);
+    const int y = (int)((i / A.nx) % A.ny);
+    const int z = (int)(i / ((long long)A.nx * A.ny));
+    const int ix = t.off[0] + x, iy = t.off[1] + y, iz = t.off[2] + z;
+    const double2 u = zmul3(f[ix], f[iy], f[iz]);
+    const double su = ipow(layer_depth(x, A.nx, A.px), A.order) +
+                      ipow(layer_depth(y, A.ny, A.py), A.order) +
+                      ipow(layer_depth(z, A.nz, A.pz), A.order);
+    const double sigma = A.sigma_max * (su < 1.0 ? su : 1.0);
+    const double2 kbg = make_double2(A.kb2, A.kb2 * sigma);
+    const double2 lap = make_double2(
+        zmul3(d2[ix], f[iy], f[iz]).x + zmul3(f[ix], d2[iy], f[iz]).x + zmul3(f[ix], f[iy], d2[iz]).x,
+        zmul3(d2[ix], f[iy], f[iz]).y + zmul3(f[ix], d2[iy], f[iz]).y + zmul3(f[ix], f[iy], d2[iz]).y);
+    const double2 diag = make_double2(lap.x - zmul(kbg, u).x, lap.y - zmul(kbg, u).y);
+    // T_c T_b u for the 3 x 3 pairs
+    const int idx[3] = {ix, iy, iz};
+    double2 tt[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        double2 v;
+        if (c == b) {
+          v = t2[idx[c]];
+        } else {
+          v = zmul(t1[idx[c]], t1[idx[b]]);
+        }
+        const int o = 3 - c - b;   // the remaining axis when c != b
+        if (c == b) {
+          const int o1 = (c + 1) % 3, o2 = (c + 2) % 3;
+          v = zmul3(v, f[idx[o1]], f[idx[o2]]);
+        } else {
+          v = zmul(v, f[idx[o]]);
+        }
+        tt[c][b] = v;
+      }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double2 sc = zmul(A.q[c], diag);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double2 w = zmul(A.q[b], tt[c][b]);
+        sc.x -= w.x;
+        sc.y -= w.y;
+      }
+      A.S[c * N + i] = make_float2((float)sc.x, (float)sc.y);
+    }
+  }
+}
+
 // streaming copy: one float4 per thread over a grid that covers the buffer
 // (the fastest plain copy form measured on this part)
 constexpr int kCopyThreads = 256;
@@ -418,7 +597,7 @@ struct cbs_plan_s {
   int k1_blocks;
   hipStream_t stream;
   // workspace carve-up
-  float2 *W, *V0, *twx, *twy, *twz, *phase;
+  float2 *W, *V0, *twx, *twy, *twz, *phase, *phx, *phy;
   double *partials, *setup_part, *hist, *metrics;
   DevState* state;
   bool have_eps;
@@ -436,7 +615,6 @@ struct cbs_plan_s {
     int enqueued;   // iterations enqueued so far
     int head, count;  // ring of outstanding quanta
     float ms;       // device time from begin to the quantum that stopped
-    float2 pol[3];
     CbsArgs args;
   } act;
   static constexpr int kRing = 4;
@@ -448,12 +626,12 @@ struct cbs_plan_s {
 namespace {
 
 struct Layout {
-  size_t W, V0, twx, twy, twz, phase, partials, setup, hist, metrics, state, total;
+  size_t W, V0, twx, twy, twz, phase, phx, phy, partials, setup, hist, metrics, state, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-int padded_pitch(int nx) { return (nx + 7) / 8 * 8; }
+int padded_pitch(int nx) { return (nx + kBrick - 1) / kBrick * kBrick; }
 
 bool layout_of(int nx, int ny, int nz, Layout& L) {
   const SizeOps* ox = find_size(nx);
@@ -473,6 +651,8 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   L.twy = take((size_t)ny * c8);
   L.twz = take((size_t)nz * c8);
   L.phase = take((size_t)nz * c8);
+  L.phx = take((size_t)nx * c8);
+  L.phy = take((size_t)ny * c8);
   L.partials = take((size_t)2 * k1b * sizeof(double));
   L.setup = take((size_t)2 * kSetupBlocks * sizeof(double));
   L.hist = take((size_t)kHistCap * sizeof(double));
@@ -486,15 +666,145 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
 // Twiddles of a two-level split n = n1 n2: t[j2 n1 + k1] = exp(-2 pi i j2 k1 / n),
 // j2 < n2, k1 < n1 (FP64 on the host, rounded to FP32).  j2 k1 < n, so the
 // angle needs no reduction, and the same table read at [k][t] serves the
-// transposed split.
-void fill_twiddles(std::vector<float2>& t, int n1, int n2) {
+// transposed split.  t holds n entries.
+void fill_twiddles(float2* t, int n1, int n2) {
   const int n = n1 * n2;
-  t.resize(n);
   for (int j2 = 0; j2 < n2; ++j2)
     for (int k1 = 0; k1 < n1; ++k1) {
       const double ang = -2.0 * M_PI * double(j2 * k1) / double(n);
       t[j2 * n1 + k1] = make_float2((float)std::cos(ang), (float)std::sin(ang));
     }
+}
+
+// Longest registered axis: the host staging arrays of the tables are this long.
+constexpr int kMaxAxis = 1024;
+
+// Argument checks of a grid and its optics (cbs_plan_create's contract).
+int check_grid(int nx, int ny, int nz, double pitch_m, double lambda0_m, double n_bg,
+               const int pml[3], int pm[3]) {
+  if (nx < 2 || ny < 2 || nz < 2) return fail(CBS_E_INVALID, "grid %dx%dx%d: each axis must be >= 2", nx, ny, nz);
+  const int dims[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    if (!cbs_axis_supported(a, dims[a]) || dims[a] > kMaxAxis)
+      return fail(CBS_E_INVALID, "axis %d length %d has no FFT specialisation", a, dims[a]);
+  if (!(pitch_m > 0) || !std::isfinite(pitch_m)) return fail(CBS_E_INVALID, "pitch must be > 0");
+  if (!(lambda0_m > 0) || !std::isfinite(lambda0_m)) return fail(CBS_E_INVALID, "lambda0 must be > 0");
+  if (!(n_bg > 0) || !std::isfinite(n_bg)) return fail(CBS_E_INVALID, "n_bg must be > 0");
+  pm[0] = pm[1] = pm[2] = 0;
+  if (pml)
+    for (int a = 0; a < 3; ++a) {
+      pm[a] = pml[a];
+      if (pm[a] < 0 || 2 * pm[a] >= dims[a])
+        return fail(CBS_E_INVALID, "pml[%d]=%d must satisfy 0 <= 2 pml < %d", a, pm[a], dims[a]);
+    }
+  return CBS_OK;
+}
+
+// Fill a plan's grid, optics and workspace carve-up (no HIP calls).
+void init_plan(cbs_plan_s* p, int nx, int ny, int nz, double pitch_m, double lambda0_m,
+               double n_bg, const int pm[3], void* workspace, hipStream_t stream) {
+  Layout L;
+  layout_of(nx, ny, nz, L);
+  p->nx = nx;
+  p->ny = ny;
+  p->nz = nz;
+  p->nxp = padded_pitch(nx);
+  for (int a = 0; a < 3; ++a) p->pml[a] = pm[a];
+  p->pitch = pitch_m;
+  p->lambda0 = lambda0_m;
+  p->n_bg = n_bg;
+  p->k0 = 2.0 * M_PI / lambda0_m;
+  p->kb = p->k0 * n_bg;
+  p->order = 2;
+  p->sigma_max = 1.0;
+  p->shift_factor = 1.1;
+  p->ox = find_size(nx);
+  p->oy = find_size(ny);
+  p->oz = find_size(nz);
+  p->k1_blocks = (int)(3LL * ((ny + p->ox->k1_rows - 1) / p->ox->k1_rows) * nz);
+  p->stream = stream;
+  char* base = static_cast<char*>(workspace);
+  p->W = reinterpret_cast<float2*>(base + L.W);
+  p->V0 = reinterpret_cast<float2*>(base + L.V0);
+  p->twx = reinterpret_cast<float2*>(base + L.twx);
+  p->twy = reinterpret_cast<float2*>(base + L.twy);
+  p->twz = reinterpret_cast<float2*>(base + L.twz);
+  p->phase = reinterpret_cast<float2*>(base + L.phase);
+  p->phx = reinterpret_cast<float2*>(base + L.phx);
+  p->phy = reinterpret_cast<float2*>(base + L.phy);
+  p->partials = reinterpret_cast<double*>(base + L.partials);
+  p->setup_part = reinterpret_cast<double*>(base + L.setup);
+  p->hist = reinterpret_cast<double*>(base + L.hist);
+  p->metrics = reinterpret_cast<double*>(base + L.metrics);
+  p->state = reinterpret_cast<DevState*>(base + L.state);
+  p->have_eps = false;
+  p->eps = -1.0;
+  p->hist_len = 0;
+}
+
+// Enqueue the twiddle tables (FP64 on the host, rounded to FP32) from host
+// staging arrays that live until the stream has consumed them (the caller
+// synchronises before they go out of scope).  The plane-wave phase tables are
+// built on the device when a solve starts (k_phase_tables).
+struct Tables {
+  float2 tx[kMaxAxis], ty[kMaxAxis], tz[kMaxAxis];
+};
+hipError_t upload_tables(cbs_plan_s* p, Tables& t) {
+  fill_twiddles(t.tx, p->ox->n1, p->ox->n2);
+  fill_twiddles(t.ty, p->oy->n1, p->oy->n2);
+  fill_twiddles(t.tz, p->oz->z1, p->oz->z2);
+  hipError_t e = hipMemcpyAsync(p->twx, t.tx, p->nx * sizeof(float2), hipMemcpyHostToDevice, p->stream);
+  e = e == hipSuccess ? hipMemcpyAsync(p->twy, t.ty, p->ny * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  e = e == hipSuccess ? hipMemcpyAsync(p->twz, t.tz, p->nz * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  return e;
+}
+
+// The potential V0, the shift eps and the validity checks of a medium
+// (cbs_set_permittivity's contract).  Synchronises the plan's stream.
+int set_permittivity_impl(cbs_plan_s* p, const void* eps_r, int dtype) {
+  if (!eps_r) return fail(CBS_E_INVALID, "eps_r is NULL");
+  if (dtype != CBS_F32 && dtype != CBS_C64) return fail(CBS_E_INVALID, "dtype must be CBS_F32 or CBS_C64");
+  p->have_eps = false;
+  SetupArgs s;
+  s.nx = p->nx;
+  s.ny = p->ny;
+  s.nz = p->nz;
+  s.px = p->pml[0];
+  s.py = p->pml[1];
+  s.pz = p->pml[2];
+  s.order = p->order;
+  s.dtype = dtype;
+  s.sigma_max = p->sigma_max;
+  const double d2 = p->pitch * p->pitch;
+  s.k0d2 = p->k0 * p->k0 * d2;
+  s.kbd2 = p->kb * p->kb * d2;
+  s.nb2 = p->n_bg * p->n_bg;
+  s.nb2f = (float)(p->n_bg * p->n_bg);
+  s.eps = eps_r;
+  s.V0 = p->V0;
+  s.part = p->setup_part;
+  hipLaunchKernelGGL(k_setup, dim3(kSetupBlocks), dim3(kSetupThreads), 0, p->stream, s);
+  HIP_LAUNCHED();
+  double part[2 * kSetupBlocks];
+  HIP_TRY(hipMemcpyAsync(part, p->setup_part, sizeof(part), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  double mx = 0.0;
+  unsigned fl = 0;
+  for (int b = 0; b < kSetupBlocks; ++b) {
+    mx = part[2 * b] > mx ? part[2 * b] : mx;
+    fl |= (unsigned)part[2 * b + 1];
+  }
+  if (fl & 1u) return fail(CBS_E_INVALID, "eps_r has non-finite values");
+  if (fl & 2u) return fail(CBS_E_INVALID, "gain medium (Im eps_r < 0) is not admissible");
+  if (fl & 4u) return fail(CBS_E_INVALID, "eps_r must equal n_bg^2 inside the absorbing layer");
+  const double floor_ = 1e-3 * p->kb * p->kb * d2;
+  const double eps_d2 = p->shift_factor * (mx > floor_ ? mx : floor_);
+  // the iteration forms (V0 - i eps) E in FP32: keep the shift far inside its range
+  if (!(eps_d2 < 1e30))
+    return fail(CBS_E_INVALID, "eps_r contrast too large for the FP32 iteration (shift %g)", eps_d2);
+  p->eps = eps_d2 / d2;
+  p->have_eps = true;
+  return CBS_OK;
 }
 
 CbsArgs base_args(cbs_plan_s* p) {
@@ -519,6 +829,12 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.phase = p->phase;
   a.partials = p->partials;
   a.k1_blocks = p->k1_blocks;
+  a.nb = 1;
+  a.sWb = 3 * a.sW;
+  a.sEb = 3 * a.sE;
+  a.phx = p->phx;
+  a.phy = p->phy;
+  a.oblique = 0;
   a.hist = p->hist;
   a.st = p->state;
   const double d2 = p->pitch * p->pitch;
@@ -530,7 +846,7 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.pfz = (float)(2.0 * M_PI / p->nz);
   a.invN = (float)(1.0 / ((double)p->nx * p->ny * p->nz));
   a.src_scale = (float)d2;
-  a.pol[0] = make_float2(1.f, 0.f);
+  a.pol[0][0] = make_float2(1.f, 0.f);
   return a;
 }
 
@@ -562,19 +878,26 @@ int enqueue_iteration(cbs_plan_s* p, const CbsArgs& a) {
 
 // reduce the residual of the last enqueued iteration (a no-op when nothing is
 // pending), so the state copied to the host is current
-int enqueue_residual(cbs_plan_s* p) {
-  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, p->partials,
-                     p->k1_blocks, p->state, p->hist);
+int enqueue_residual(cbs_plan_s* p, const CbsArgs& a) {
+  hipLaunchKernelGGL(k_residual, dim3(1), dim3(kResThreads), 0, p->stream, a.partials,
+                     a.k1_blocks, a.nb, p->state, p->hist);
   HIP_LAUNCHED();
   return CBS_OK;
 }
 
 // Start a solve: device state, point-source amplitude, optional warm-start
 // conversion to the scattered field, and the prologue (W = V E + S, forward x).
-int begin_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* src,
-                const void* E_fwd, const float2 pol[3]) {
-  auto& A = p->act;
-  if (A.on) return fail(CBS_E_STATE, "a solve is already in progress on this plan");
+// Device state, point-source amplitude and warm-start conversion of a solve.
+int enqueue_solve_start(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* src,
+                        const void* E_fwd, const Kvec& kv) {
+  if (a.src == SRC_PLANE) {
+    // the incident plane waves' phase tables (built before anything reads them)
+    const int n = kv.nb * (p->nx + p->ny + p->nz);
+    hipLaunchKernelGGL(k_phase_tables, dim3((n + 255) / 256), dim3(256), 0, p->stream,
+                       const_cast<float2*>(a.phx), const_cast<float2*>(a.phy),
+                       const_cast<float2*>(a.phase), p->nx, p->ny, p->nz, kv);
+    HIP_LAUNCHED();
+  }
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, o->tol,
                      o->max_iter, (o->flags & CBS_RECORD_HISTORY) ? 1 : 0);
   HIP_LAUNCHED();
@@ -588,13 +911,20 @@ int begin_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* 
                        make_float2((float)src->amp[2][0], (float)src->amp[2][1]));
     HIP_LAUNCHED();
   }
-  const bool plane = a.src == SRC_PLANE;
   a.warm = (o->flags & CBS_WARM_START) ? 1 : 0;
-  if (a.warm && plane) {
-    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, a.E, p->phase, p->nx,
-                       p->ny, p->nz, pol[0], pol[1], pol[2], -1.0f);
+  if (a.warm && a.src == SRC_PLANE) {
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, a, -1.0f);
     HIP_LAUNCHED();
   }
+  return CBS_OK;
+}
+
+int begin_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* src,
+                const void* E_fwd, const Kvec& kv) {
+  auto& A = p->act;
+  if (A.on) return fail(CBS_E_STATE, "a solve is already in progress on this plan");
+  if (int rc = enqueue_solve_start(p, a, o, src, E_fwd, kv)) return rc;
+  const bool plane = a.src == SRC_PLANE;
   HIP_TRY(hipEventRecord(p->ev0, p->stream));
   p->ox->k1(a, K1_FWD, p->stream);
   HIP_LAUNCHED();
@@ -606,7 +936,6 @@ int begin_solve(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* 
   A.enqueued = 0;
   A.head = A.count = 0;
   A.ms = 0.f;
-  for (int c = 0; c < 3; ++c) A.pol[c] = pol[c];
   A.args = a;
   std::memset(&p->last, 0, sizeof(DevState));
   return CBS_OK;
@@ -627,7 +956,7 @@ int advance_solve(cbs_plan_s* p, int iters) {
     if (rc != CBS_OK) return rc;
   }
   A.enqueued += q;
-  if (int rc = enqueue_residual(p)) return rc;
+  if (int rc = enqueue_residual(p, A.args)) return rc;
   const int slot = (A.head + A.count) % cbs_plan_s::kRing;
   HIP_TRY(hipMemcpyAsync(&p->mirror[slot], p->state, sizeof(DevState), hipMemcpyDeviceToHost,
                          p->stream));
@@ -674,8 +1003,7 @@ int end_solve(cbs_plan_s* p, cbs_stats* stats) {
   if (!A.stopped) return fail(CBS_E_STATE, "solve has not stopped yet (advance further)");
   A.on = false;
   if (A.plane && !(A.flags & CBS_RETURN_SCATTERED)) {
-    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, A.args.E, p->phase,
-                       p->nx, p->ny, p->nz, A.pol[0], A.pol[1], A.pol[2], 1.0f);
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, A.args, 1.0f);
     HIP_LAUNCHED();
   }
   const DevState& hs = p->last;
@@ -715,12 +1043,39 @@ int run_blocking(cbs_plan_s* p, int check_every, cbs_stats* stats) {
 // Argument checks and source set-up shared by the blocking and the
 // asynchronous entry points.
 int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cbs_opts* o,
-            CbsArgs& a, float2 pol[3]);
+            CbsArgs& a, Kvec& kv);
 
-int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, float2 pol[3]) {
+// Illumination b of a plane-wave source: polarisation (x if all zero) and the
+// wave vector from the transverse direction cosines (normal incidence if zero).
+int set_plane_wave(cbs_plan_s* p, CbsArgs& a, Kvec& kv, int b, const cbs_source* src) {
+  a.pol[b][0] = make_float2(1.f, 0.f);
+  a.pol[b][1] = a.pol[b][2] = make_float2(0.f, 0.f);
+  double sx = 0.0, sy = 0.0;
+  if (src) {
+    bool any = false;
+    for (int c = 0; c < 3; ++c) any |= (src->pol[c][0] != 0.0 || src->pol[c][1] != 0.0);
+    if (any)
+      for (int c = 0; c < 3; ++c)
+        a.pol[b][c] = make_float2((float)src->pol[c][0], (float)src->pol[c][1]);
+    sx = src->dir[0];
+    sy = src->dir[1];
+  }
+  if (!std::isfinite(sx) || !std::isfinite(sy) || !(sx * sx + sy * sy < 1.0))
+    return fail(CBS_E_INVALID, "plane-wave direction (%g, %g): need sx^2 + sy^2 < 1", sx, sy);
+  const double kbd = p->kb * p->pitch;
+  kv.kd[b][0] = kbd * sx;
+  kv.kd[b][1] = kbd * sy;
+  kv.kd[b][2] = kbd * std::sqrt(1.0 - sx * sx - sy * sy);
+  if (sx != 0.0 || sy != 0.0) a.oblique = 1;
+  return CBS_OK;
+}
+
+int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, Kvec& kv) {
   const int kind = src ? src->kind : CBS_SRC_PLANE_WAVE;
-  pol[0] = make_float2(1.f, 0.f);
-  pol[1] = pol[2] = make_float2(0.f, 0.f);
+  kv.nb = 1;
+  for (int c = 0; c < 3; ++c) kv.kd[0][c] = 0.0;
+  a.pol[0][0] = make_float2(1.f, 0.f);
+  a.pol[0][1] = a.pol[0][2] = make_float2(0.f, 0.f);
   switch (kind) {
     case CBS_SRC_NONE:
       a.src = SRC_NONE;
@@ -728,13 +1083,7 @@ int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, f
     case CBS_SRC_PLANE_WAVE: {
       if (adjoint) return fail(CBS_E_INVALID, "adjoint source cannot be a plane wave");
       a.src = SRC_PLANE;
-      if (src) {
-        bool any = false;
-        for (int c = 0; c < 3; ++c) any |= (src->pol[c][0] != 0.0 || src->pol[c][1] != 0.0);
-        if (any)
-          for (int c = 0; c < 3; ++c)
-            pol[c] = make_float2((float)src->pol[c][0], (float)src->pol[c][1]);
-      }
+      if (int rc = set_plane_wave(p, a, kv, 0, src)) return rc;
       break;
     }
     case CBS_SRC_FIELD:
@@ -757,14 +1106,11 @@ int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, f
     default:
       return fail(CBS_E_INVALID, "unknown source kind %d", kind);
   }
-  a.pol[0] = pol[0];
-  a.pol[1] = pol[1];
-  a.pol[2] = pol[2];
   return CBS_OK;
 }
 
 int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cbs_opts* o,
-            CbsArgs& a, float2 pol[3]) {
+            CbsArgs& a, Kvec& kv) {
   int rc = check_plan(p, true);
   if (rc) return rc;
   if ((rc = check_opts(o))) return rc;
@@ -776,7 +1122,7 @@ int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cb
       return fail(CBS_E_INVALID, "adjoint source must be POINT, FIELD or FIELD_CONJ");
   }
   a = base_args(p);
-  if ((rc = set_source(p, a, src, adjoint != 0, pol))) return rc;
+  if ((rc = set_source(p, a, src, adjoint != 0, kv))) return rc;
   a.E = static_cast<float2*>(E);
   return CBS_OK;
 }
@@ -784,6 +1130,8 @@ int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cb
 }  // namespace
 
 extern "C" {
+
+
 
 size_t cbs_plan_workspace_bytes(int nx, int ny, int nz) {
   if (nx < 2 || ny < 2 || nz < 2) return 0;
@@ -806,21 +1154,8 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
                     void* stream) {
   if (!out) return fail(CBS_E_INVALID, "out is NULL");
   *out = nullptr;
-  if (nx < 2 || ny < 2 || nz < 2) return fail(CBS_E_INVALID, "grid %dx%dx%d: each axis must be >= 2", nx, ny, nz);
-  const int dims[3] = {nx, ny, nz};
-  for (int a = 0; a < 3; ++a)
-    if (!cbs_axis_supported(a, dims[a]))
-      return fail(CBS_E_INVALID, "axis %d length %d has no FFT specialisation", a, dims[a]);
-  if (!(pitch_m > 0) || !std::isfinite(pitch_m)) return fail(CBS_E_INVALID, "pitch must be > 0");
-  if (!(lambda0_m > 0) || !std::isfinite(lambda0_m)) return fail(CBS_E_INVALID, "lambda0 must be > 0");
-  if (!(n_bg > 0) || !std::isfinite(n_bg)) return fail(CBS_E_INVALID, "n_bg must be > 0");
-  int pm[3] = {0, 0, 0};
-  if (pml)
-    for (int a = 0; a < 3; ++a) {
-      pm[a] = pml[a];
-      if (pm[a] < 0 || 2 * pm[a] >= dims[a])
-        return fail(CBS_E_INVALID, "pml[%d]=%d must satisfy 0 <= 2 pml < %d", a, pm[a], dims[a]);
-    }
+  int pm[3];
+  if (int rc = check_grid(nx, ny, nz, pitch_m, lambda0_m, n_bg, pml, pm)) return rc;
   Layout L;
   layout_of(nx, ny, nz, L);
   if (!workspace) return fail(CBS_E_WORKSPACE, "workspace is NULL");
@@ -831,48 +1166,8 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
 
   cbs_plan_s* p = new (std::nothrow) cbs_plan_s();
   if (!p) return fail(CBS_E_INVALID, "out of host memory");
-  p->nx = nx;
-  p->ny = ny;
-  p->nz = nz;
-  p->nxp = padded_pitch(nx);
-  for (int a = 0; a < 3; ++a) p->pml[a] = pm[a];
-  p->pitch = pitch_m;
-  p->lambda0 = lambda0_m;
-  p->n_bg = n_bg;
-  p->k0 = 2.0 * M_PI / lambda0_m;
-  p->kb = p->k0 * n_bg;
-  p->order = 2;
-  p->sigma_max = 1.0;
-  p->shift_factor = 1.1;
-  p->ox = find_size(nx);
-  p->oy = find_size(ny);
-  p->oz = find_size(nz);
-  p->k1_blocks = (int)(3LL * ((ny + p->ox->k1_rows - 1) / p->ox->k1_rows) * nz);
-  p->stream = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(workspace);
-  p->W = reinterpret_cast<float2*>(base + L.W);
-  p->V0 = reinterpret_cast<float2*>(base + L.V0);
-  p->twx = reinterpret_cast<float2*>(base + L.twx);
-  p->twy = reinterpret_cast<float2*>(base + L.twy);
-  p->twz = reinterpret_cast<float2*>(base + L.twz);
-  p->phase = reinterpret_cast<float2*>(base + L.phase);
-  p->partials = reinterpret_cast<double*>(base + L.partials);
-  p->setup_part = reinterpret_cast<double*>(base + L.setup);
-  p->hist = reinterpret_cast<double*>(base + L.hist);
-  p->metrics = reinterpret_cast<double*>(base + L.metrics);
-  p->state = reinterpret_cast<DevState*>(base + L.state);
-  p->have_eps = false;
-  p->eps = -1.0;
-  p->hist_len = 0;
-
-  std::vector<float2> tx, ty, tz, ph(nz);
-  fill_twiddles(tx, p->ox->n1, p->ox->n2);
-  fill_twiddles(ty, p->oy->n1, p->oy->n2);
-  fill_twiddles(tz, p->oz->z1, p->oz->z2);
-  for (int k = 0; k < nz; ++k) {
-    const double ang = p->kb * pitch_m * k;
-    ph[k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-  }
+  init_plan(p, nx, ny, nz, pitch_m, lambda0_m, n_bg, pm, workspace,
+            static_cast<hipStream_t>(stream));
   // events are created null and destroyed by cleanup whatever succeeded
   auto cleanup = [&](int rc) {
     if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -893,14 +1188,14 @@ int cbs_plan_create(cbs_plan_t* out, int nx, int ny, int nz, double pitch_m, dou
     if (hipEventCreate(&p->evq[i]) != hipSuccess) return cleanup(fail(CBS_E_HIP, "hipEventCreate failed"));
   if (hipHostMalloc((void**)&p->mirror, cbs_plan_s::kRing * sizeof(DevState), hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(CBS_E_HIP, "hipHostMalloc of the state mirror failed"));
-  hipError_t e = hipSuccess;
-  e = e == hipSuccess ? hipMemcpyAsync(p->twx, tx.data(), nx * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
-  e = e == hipSuccess ? hipMemcpyAsync(p->twy, ty.data(), ny * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
-  e = e == hipSuccess ? hipMemcpyAsync(p->twz, tz.data(), nz * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
-  e = e == hipSuccess ? hipMemcpyAsync(p->phase, ph.data(), nz * sizeof(float2), hipMemcpyHostToDevice, p->stream) : e;
+  Tables* t = new (std::nothrow) Tables;
+  if (!t) return cleanup(fail(CBS_E_INVALID, "out of host memory"));
+  hipError_t e = upload_tables(p, *t);
   e = e == hipSuccess ? hipMemsetAsync(p->W, 0, L.V0 - L.W, p->stream) : e;
   e = e == hipSuccess ? hipMemsetAsync(p->state, 0, sizeof(DevState), p->stream) : e;
-  e = e == hipSuccess ? hipStreamSynchronize(p->stream) : e;
+  const hipError_t es = hipStreamSynchronize(p->stream);
+  delete t;
+  e = e == hipSuccess ? es : e;
   if (e != hipSuccess) return cleanup(fail(CBS_E_HIP, "plan upload: %s", hipGetErrorString(e)));
   *out = p;
   return CBS_OK;
@@ -931,50 +1226,7 @@ int cbs_plan_set_shift_factor(cbs_plan_t p, double kappa) {
 int cbs_set_permittivity(cbs_plan_t p, const void* eps_r, int dtype) {
   int rc = check_plan(p, false);
   if (rc) return rc;
-  if (!eps_r) return fail(CBS_E_INVALID, "eps_r is NULL");
-  if (dtype != CBS_F32 && dtype != CBS_C64) return fail(CBS_E_INVALID, "dtype must be CBS_F32 or CBS_C64");
-  p->have_eps = false;
-  SetupArgs s;
-  s.nx = p->nx;
-  s.ny = p->ny;
-  s.nz = p->nz;
-  s.px = p->pml[0];
-  s.py = p->pml[1];
-  s.pz = p->pml[2];
-  s.order = p->order;
-  s.dtype = dtype;
-  s.sigma_max = p->sigma_max;
-  const double d2 = p->pitch * p->pitch;
-  s.k0d2 = p->k0 * p->k0 * d2;
-  s.kbd2 = p->kb * p->kb * d2;
-  s.nb2 = p->n_bg * p->n_bg;
-  s.nb2f = (float)(p->n_bg * p->n_bg);
-  s.eps = eps_r;
-  s.V0 = p->V0;
-  s.part = p->setup_part;
-  hipLaunchKernelGGL(k_setup, dim3(kSetupBlocks), dim3(kSetupThreads), 0, p->stream, s);
-  HIP_LAUNCHED();
-  std::vector<double> part(2 * kSetupBlocks);
-  HIP_TRY(hipMemcpyAsync(part.data(), p->setup_part, part.size() * sizeof(double),
-                         hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  double mx = 0.0;
-  unsigned fl = 0;
-  for (int b = 0; b < kSetupBlocks; ++b) {
-    mx = part[2 * b] > mx ? part[2 * b] : mx;
-    fl |= (unsigned)part[2 * b + 1];
-  }
-  if (fl & 1u) return fail(CBS_E_INVALID, "eps_r has non-finite values");
-  if (fl & 2u) return fail(CBS_E_INVALID, "gain medium (Im eps_r < 0) is not admissible");
-  if (fl & 4u) return fail(CBS_E_INVALID, "eps_r must equal n_bg^2 inside the absorbing layer");
-  const double floor_ = 1e-3 * p->kb * p->kb * d2;
-  const double eps_d2 = p->shift_factor * (mx > floor_ ? mx : floor_);
-  // the iteration forms (V0 - i eps) E in FP32: keep the shift far inside its range
-  if (!(eps_d2 < 1e30))
-    return fail(CBS_E_INVALID, "eps_r contrast too large for the FP32 iteration (shift %g)", eps_d2);
-  p->eps = eps_d2 / d2;
-  p->have_eps = true;
-  return CBS_OK;
+  return set_permittivity_impl(p, eps_r, dtype);
 }
 
 double cbs_eps_shift(cbs_plan_t p) { return (p && p->have_eps) ? p->eps : -1.0; }
@@ -982,30 +1234,30 @@ double cbs_eps_shift(cbs_plan_t p) { return (p && p->have_eps) ? p->eps : -1.0; 
 int cbs_solve(cbs_plan_t p, const cbs_source* src, void* E_dev, const cbs_opts* o,
               cbs_stats* stats) {
   CbsArgs a;
-  float2 pol[3];
-  int rc = prepare(p, 0, src, E_dev, o, a, pol);
+  Kvec kv;
+  int rc = prepare(p, 0, src, E_dev, o, a, kv);
   if (rc) return rc;
-  if ((rc = begin_solve(p, a, o, src, nullptr, pol))) return rc;
+  if ((rc = begin_solve(p, a, o, src, nullptr, kv))) return rc;
   return run_blocking(p, o->check_every, stats);
 }
 
 int cbs_adjoint_solve(cbs_plan_t p, const void* E_fwd, const cbs_source* adj, void* E_adj,
                       const cbs_opts* o, cbs_stats* stats) {
   CbsArgs a;
-  float2 pol[3];
-  int rc = prepare(p, 1, adj, E_adj, o, a, pol);
+  Kvec kv;
+  int rc = prepare(p, 1, adj, E_adj, o, a, kv);
   if (rc) return rc;
-  if ((rc = begin_solve(p, a, o, adj, E_fwd, pol))) return rc;
+  if ((rc = begin_solve(p, a, o, adj, E_fwd, kv))) return rc;
   return run_blocking(p, o->check_every, stats);
 }
 
 int cbs_solve_begin(cbs_plan_t p, int adjoint, const void* E_fwd, const cbs_source* src,
                     void* E_dev, const cbs_opts* o) {
   CbsArgs a;
-  float2 pol[3];
-  int rc = prepare(p, adjoint, src, E_dev, o, a, pol);
+  Kvec kv;
+  int rc = prepare(p, adjoint, src, E_dev, o, a, kv);
   if (rc) return rc;
-  return begin_solve(p, a, o, src, adjoint ? E_fwd : nullptr, pol);
+  return begin_solve(p, a, o, src, adjoint ? E_fwd : nullptr, kv);
 }
 
 int cbs_solve_advance(cbs_plan_t p, int iters) {
@@ -1026,6 +1278,82 @@ int cbs_solve_end(cbs_plan_t p, cbs_stats* stats) {
   int rc = check_plan(p, true);
   if (rc) return rc;
   return end_solve(p, stats);
+}
+
+namespace {
+struct BatchLayout {
+  size_t W, partials, phx, phy, phz, total;
+};
+bool batch_layout(int nx, int ny, int nz, int count, BatchLayout& B) {
+  const SizeOps* ox = find_size(nx);
+  if (!ox || count < 1 || count > kMaxIllum) return false;
+  const long long k1b = 3LL * ((ny + ox->k1_rows - 1) / ox->k1_rows) * nz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  // the fields follow each other with no padding: W_b = W_0 + 3 b sW
+  B.W = take((size_t)count * 3 * nz * ny * padded_pitch(nx) * sizeof(float2));
+  B.partials = take((size_t)count * 2 * k1b * sizeof(double));
+  B.phx = take((size_t)count * nx * sizeof(float2));
+  B.phy = take((size_t)count * ny * sizeof(float2));
+  B.phz = take((size_t)count * nz * sizeof(float2));
+  B.total = off;
+  return true;
+}
+}  // namespace
+
+size_t cbs_batch_workspace_bytes(int nx, int ny, int nz, int count) {
+  if (!cbs_plan_workspace_bytes(nx, ny, nz)) return 0;
+  BatchLayout B;
+  return batch_layout(nx, ny, nz, count, B) ? B.total : 0;
+}
+
+int cbs_solve_batch(cbs_plan_t p, int count, const cbs_source* srcs, void* E_dev,
+                    const cbs_opts* o, cbs_stats* stats, void* work, size_t work_bytes) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (count < 1 || count > kMaxIllum)
+    return fail(CBS_E_INVALID, "count %d outside [1, %d]", count, kMaxIllum);
+  if (!srcs || !E_dev) return fail(CBS_E_INVALID, "sources or the output field is NULL");
+  BatchLayout B;
+  batch_layout(p->nx, p->ny, p->nz, count, B);
+  if (!work) return fail(CBS_E_WORKSPACE, "batch workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(CBS_E_WORKSPACE, "batch workspace must be 256-byte aligned");
+  if (work_bytes < B.total)
+    return fail(CBS_E_WORKSPACE, "batch workspace %zu bytes < required %zu", work_bytes, B.total);
+  CbsArgs a = base_args(p);
+  Kvec kv;
+  kv.nb = count;
+  a.src = SRC_PLANE;
+  for (int b = 0; b < count; ++b) {
+    if (srcs[b].kind != CBS_SRC_PLANE_WAVE)
+      return fail(CBS_E_INVALID, "batched source %d is not a plane wave", b);
+    if ((rc = set_plane_wave(p, a, kv, b, &srcs[b]))) return rc;
+  }
+  char* base = static_cast<char*>(work);
+  a.nb = count;
+  a.W = reinterpret_cast<float2*>(base + B.W);
+  a.partials = reinterpret_cast<double*>(base + B.partials);
+  a.phx = reinterpret_cast<float2*>(base + B.phx);
+  a.phy = reinterpret_cast<float2*>(base + B.phy);
+  a.phase = reinterpret_cast<float2*>(base + B.phz);
+  a.E = static_cast<float2*>(E_dev);
+  if ((rc = begin_solve(p, a, o, nullptr, nullptr, kv))) return rc;
+  cbs_stats st;
+  rc = run_blocking(p, o->check_every, &st);
+  if (rc < 0 && rc != CBS_E_DIVERGED) return rc;
+  if (stats)
+    for (int b = 0; b < count; ++b) {
+      stats[b] = st;
+      stats[b].residual = p->last.eta_b[b];
+      stats[b].converged = p->last.eta_b[b] <= o->tol ? 1 : 0;
+    }
+  return rc;
 }
 
 int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out) {
@@ -1185,6 +1513,69 @@ int cbs_lens_metrics(cbs_plan_t p, const void* E, const int lo[3], const int hi[
   return CBS_OK;
 }
 
+int cbs_tfsf_source(cbs_plan_t p, const cbs_source* src, const int lo[3], const int hi[3],
+                    void* S_dev) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!S_dev || !lo || !hi) return fail(CBS_E_INVALID, "NULL argument");
+  if (src && src->kind != CBS_SRC_PLANE_WAVE)
+    return fail(CBS_E_INVALID, "the TF/SF source injects a plane wave (kind PLANE_WAVE)");
+  if (p->act.on) return fail(CBS_E_STATE, "a solve is in progress on this plan");
+  const int dims[3] = {p->nx, p->ny, p->nz};
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] < 0 || hi[a] > dims[a] || lo[a] >= hi[a])
+      return fail(CBS_E_INVALID, "box axis %d [%d,%d) empty or outside [0,%d)", a, lo[a], hi[a],
+                  dims[a]);
+  CbsArgs a = base_args(p);
+  Kvec kv;
+  kv.nb = 1;
+  if ((rc = set_plane_wave(p, a, kv, 0, src))) return rc;
+  TfsfAssemble A;
+  TfsfArgs& t = A.t;
+  t.ntot = p->nx + p->ny + p->nz;
+  for (int ax = 0; ax < 3; ++ax) {
+    t.n[ax] = dims[ax];
+    t.lo[ax] = lo[ax];
+    t.hi[ax] = hi[ax];
+    t.kd[ax] = kv.kd[0][ax];
+  }
+  t.off[0] = 0;
+  t.off[1] = p->nx;
+  t.off[2] = p->nx + p->ny;
+  t.pitch = p->pitch;
+  t.tab = reinterpret_cast<double2*>(p->W);   // the spectral work field is free between solves
+  A.nx = p->nx;
+  A.ny = p->ny;
+  A.nz = p->nz;
+  A.px = p->pml[0];
+  A.py = p->pml[1];
+  A.pz = p->pml[2];
+  A.order = p->order;
+  A.sigma_max = p->sigma_max;
+  A.kb2 = p->kb * p->kb;
+  for (int c = 0; c < 3; ++c) {
+    double re = c == 0 ? 1.0 : 0.0, im = 0.0;
+    if (src) {
+      bool any = false;
+      for (int k = 0; k < 3; ++k) any |= (src->pol[k][0] != 0.0 || src->pol[k][1] != 0.0);
+      if (any) {
+        re = src->pol[c][0];
+        im = src->pol[c][1];
+      }
+    }
+    A.q[c] = make_double2(re, im);
+  }
+  A.S = static_cast<float2*>(S_dev);
+  const dim3 g1((t.ntot + 127) / 128), b1(128);
+  hipLaunchKernelGGL(k_tfsf_forward, g1, b1, 0, p->stream, t);
+  HIP_LAUNCHED();
+  hipLaunchKernelGGL(k_tfsf_inverse, g1, b1, 0, p->stream, t);
+  HIP_LAUNCHED();
+  hipLaunchKernelGGL(k_tfsf_assemble, dim3(2048), dim3(256), 0, p->stream, A);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
 int cbs_apply_green(cbs_plan_t p, const void* in, void* out) {
   int rc = check_plan(p, true);
   if (rc) return rc;
@@ -1210,9 +1601,11 @@ int cbs_time_passes(cbs_plan_t p, void* E_dev, int iters, float* ms_out) {
   if (rc) return rc;
   if (!E_dev || !ms_out || iters < 1) return fail(CBS_E_INVALID, "bad arguments");
   CbsArgs a = base_args(p);
-  float2 pol[3];
-  if ((rc = set_source(p, a, nullptr, false, pol))) return rc;
+  Kvec kv;
+  if ((rc = set_source(p, a, nullptr, false, kv))) return rc;
   a.E = static_cast<float2*>(E_dev);
+  hipLaunchKernelGGL(k_phase_tables, dim3(8), dim3(256), 0, p->stream, p->phx, p->phy, p->phase,
+                     p->nx, p->ny, p->nz, kv);
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, p->stream, p->state, 0.0, iters, 0);
   HIP_LAUNCHED();
   p->ox->k1(a, K1_FWD, p->stream);

@@ -44,6 +44,8 @@ enum SrcKind : int { SRC_NONE = 0, SRC_PLANE = 1, SRC_FIELD = 2, SRC_POINT = 3, 
 enum K1Mode : int { K1_FWD = 0, K1_ITER = 1, K1_INV = 2 };
 
 constexpr int kHistCap = 1 << 16;
+// Illuminations one batched solve advances together (same medium, own sources).
+constexpr int kMaxIllum = 8;
 
 // The spectral work field W is stored in bricks of 8 x-columns:
 //   W[c][z][x / 8][y][x % 8]   (x padded to nxp = 8 * gx columns)
@@ -68,6 +70,7 @@ struct DevState {
   float2 amp[3];   // point-source amplitude (already scaled by d^2)
   int record;      // keep eta history
   int pending;     // the x pass wrote residual partials that are not reduced yet
+  double eta_b[kMaxIllum];   // last relative update norm of each illumination
 };
 
 // Fixed-order sum of the per-block partials, then the stopping rule.  The
@@ -76,42 +79,58 @@ struct DevState {
 // one wave in a fixed order, so the result is the same double whichever kernel
 // and block shape runs it (the lagged reduction in the y pass and the
 // quantum-end k_residual must agree bit for bit: which of them reduces a given
-// iteration depends on where the host's quanta end).  red holds 2 kResStreams
-// doubles of LDS; THREADS is any multiple of 64.
+// iteration depends on where the host's quanta end).  A batched solve has nb
+// illuminations with per_b partials each: each gets its own eta, and the solve
+// stops when the largest meets tol.  red holds 2 kResStreams doubles of LDS;
+// THREADS is any multiple of 64.
 constexpr int kResStreams = 256;
 template <int THREADS>
-__device__ __forceinline__ void residual_finish(const double* part, int nb, DevState* st,
-                                                double* hist, double* red) {
+__device__ __forceinline__ void residual_finish(const double* part, int per_b, int nb,
+                                                DevState* st, double* hist, double* red) {
   static_assert(THREADS % 64 == 0, "whole waves");
-  for (int s = threadIdx.x; s < kResStreams; s += THREADS) {
-    double a = 0.0, b = 0.0;
-    for (int i = s; i < nb; i += kResStreams) {
-      a += __builtin_nontemporal_load(part + 2 * i);
-      b += __builtin_nontemporal_load(part + 2 * i + 1);
+  double eta = 0.0;      // the largest eta (meaningful in thread 0)
+  bool bad = false;      // a non-finite eta
+  for (int ib = 0; ib < nb; ++ib) {
+    const double* pb = part + 2LL * ib * per_b;
+    for (int s = threadIdx.x; s < kResStreams; s += THREADS) {
+      double a = 0.0, b = 0.0;
+      for (int i = s; i < per_b; i += kResStreams) {
+        a += __builtin_nontemporal_load(pb + 2 * i);
+        b += __builtin_nontemporal_load(pb + 2 * i + 1);
+      }
+      red[s] = a;
+      red[kResStreams + s] = b;
     }
-    red[s] = a;
-    red[kResStreams + s] = b;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int l = threadIdx.x;
+      double nd = red[l], ne = red[kResStreams + l];
+      #pragma unroll
+      for (int q = 64; q < kResStreams; q += 64) {
+        nd += red[l + q];
+        ne += red[kResStreams + l + q];
+      }
+      #pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        nd += __shfl_xor(nd, o, 64);
+        ne += __shfl_xor(ne, o, 64);
+      }
+      if (l == 0) {
+        double e;
+        if (ne > 0.0)
+          e = sqrt(nd / ne);
+        else
+          e = (nd == 0.0) ? 0.0 : INFINITY;
+        st->eta_b[ib] = e;
+        if (!isfinite(e)) bad = true;
+        else if (e > eta) eta = e;
+      }
+    }
+    __syncthreads();   // red is rewritten for the next illumination
   }
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    const int l = threadIdx.x;
-    double nd = red[l], ne = red[kResStreams + l];
-    #pragma unroll
-    for (int q = 64; q < kResStreams; q += 64) {
-      nd += red[l + q];
-      ne += red[kResStreams + l + q];
-    }
-    #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      nd += __shfl_xor(nd, o, 64);
-      ne += __shfl_xor(ne, o, 64);
-    }
-    if (l == 0) {
-      double eta;
-      if (ne > 0.0)
-        eta = sqrt(nd / ne);
-      else
-        eta = (nd == 0.0) ? 0.0 : INFINITY;
+  if (threadIdx.x == 0) {
+    if (bad) eta = NAN;
+    {
       const int it = st->iter + 1;
       st->iter = it;
       st->eta = eta;
@@ -131,8 +150,8 @@ __device__ __forceinline__ void residual_finish(const double* part, int nb, DevS
 }
 
 struct CbsArgs {
-  int nx, ny, nz, nxp;          // grid, padded row length of W (8 * gx)
-  int gx, gy;                   // x bricks (nxp / 8), x-pass row groups (ceil(ny / rows))
+  int nx, ny, nz, nxp;          // grid, padded row length of W (kBrick * gx)
+  int gx, gy;                   // x bricks (nxp / kBrick), x-pass row groups (ceil(ny / rows))
   int px, py, pz;               // absorbing layer per side
   long long sW;                 // component stride of W  (nz * ny * nxp)
   long long sE;                 // component stride of E  (nz * ny * nx)
@@ -142,11 +161,16 @@ struct CbsArgs {
   const float2* twx;            // x split n1 x n2: twx[j2 n1 + k1] = exp(-2 pi i j2 k1 / nx)
   const float2* twy;            // same layout for the y split
   const float2* twz;            // same layout for the z split
-  const float2* phase;          // exp(i kb d k), k < nz
+  const float2* phase;          // [nb][nz] exp(i kz d z) of each illumination's plane wave
   const float2* fin;            // FIELD source / Green input
   float2* fout;                 // Green output
   double* partials;             // 2 doubles per K1 block
-  int k1_blocks;                // number of K1 blocks (partials to reduce)
+  int k1_blocks;                // K1 blocks per illumination (partials to reduce for each)
+  int nb;                       // illuminations advanced together (1: an ordinary solve)
+  long long sWb, sEb;           // stride between illuminations in W (3 sW) and E (3 sE)
+  const float2* phx;            // [nb][nx] exp(i kx d x) of each illumination's plane wave
+  const float2* phy;            // [nb][ny] exp(i ky d y)
+  int oblique;                  // some illumination has kx or ky != 0 (phx, phy not all 1)
   int k1_prio;                  // x-pass: raise wave priority for the load phase (set by launch_k1)
   int ky_prio;                  // y pass: the same (set by launch_ky)
   double* hist;                 // residual history
@@ -155,7 +179,7 @@ struct CbsArgs {
   int warm;                     // K1_FWD: W = V E + S from E (else E = 0)
   int green_in;                 // K1_FWD: W = fin
   int r0x, r0y, r0z;
-  float2 pol[3];
+  float2 pol[kMaxIllum][3];     // polarisation of each illumination's plane wave
   float src_scale;              // d^2: physical (1/m^2) sources and Green inputs
   float eps, inv_eps, kb2;      // eps d^2, 1/(eps d^2), kb^2 d^2
   float pfx, pfy, pfz;          // 2 pi / n_a
@@ -313,11 +337,13 @@ k1_xpass(CbsArgs a) {
   TwStage<N, G::THREADS> tws;
   tws.issue(a.twx, tid);
 
-  // block -> (component, row group, z); the three components of the same rows
-  // are adjacent in the remapped order so V0 is shared in one L2
-  const unsigned L = xcd_remap(blockIdx.x, 3u * (unsigned)a.gy * (unsigned)a.nz);
-  const int c = (int)(L % 3u);
-  const unsigned rest = L / 3u;
+  // block -> (illumination, component, row group, z); the 3 nb components of
+  // the same rows are adjacent in the remapped order so V0 is shared in one L2
+  const unsigned per = 3u * (unsigned)a.nb;
+  const unsigned L = xcd_remap(blockIdx.x, per * (unsigned)a.gy * (unsigned)a.nz);
+  const int cc = (int)(L % per);
+  const int ib = cc / 3, c = cc - 3 * ib;
+  const unsigned rest = L / per;
   const int yg = (int)(rest % (unsigned)a.gy);
   const int z = (int)(rest / (unsigned)a.gy);
   const int y0 = yg * R;
@@ -329,9 +355,9 @@ k1_xpass(CbsArgs a) {
   const int y = y0 + (ok ? line : 0);
   float2* Lr = lds + (line < R ? line : 0) * N;
   // W bricks of this (component, z, row group): brick xt starts at wb + xt * ny * 8
-  float2* wb = a.W + c * a.sW + ((long long)z * a.gx * a.ny + y0) * kBrick;
+  float2* wb = a.W + ib * a.sWb + c * a.sW + ((long long)z * a.gx * a.ny + y0) * kBrick;
   const long long bstride = (long long)a.ny * kBrick;
-  const long long ebase = c * a.sE + ((long long)z * a.ny + y) * a.nx;  // E / fin / fout row
+  const long long ebase = ib * a.sEb + c * a.sE + ((long long)z * a.ny + y) * a.nx;  // E / fin / fout row
   const long long vbase = ((long long)z * a.ny + y) * a.nx;             // V0 row
 
   float2 v[N2];  // thread t (< N1): element t + N1 m, m < N2
@@ -350,7 +376,7 @@ k1_xpass(CbsArgs a) {
 
   // element x of this thread's row in the bricks
   float2* wrow = wb + line * kBrick;
-  auto wat = [&](int x) -> float2& { return wrow[(x >> 3) * bstride + (x & 7)]; };
+  auto wat = [&](int x) -> float2& { return wrow[(x / kBrick) * bstride + (x % kBrick)]; };
   // inverse level A input: thread j2 = t < N2 holds row[j2 + N2 j1]
   float2 b[N1];
   auto load_a = [&]() {
@@ -389,9 +415,11 @@ k1_xpass(CbsArgs a) {
   if (ok && t < N1) {
     const bool yin = (y >= a.py) && (y < a.ny - a.py);
     const bool zin = (z >= a.pz) && (z < a.nz - a.pz);
-    const float2 ph = a.phase[z];
-    const float2 pc = c == 0 ? a.pol[0] : (c == 1 ? a.pol[1] : a.pol[2]);
-    const float2 spl = cmul(ph, pc);  // pol_c exp(i kb z)
+    const float2 ph = a.phase[ib * a.nz + z];
+    const float2 pc = a.pol[ib][c];
+    // pol_c exp(i (ky y + kz z)); the x phase joins per element when oblique
+    const float2 spl = a.oblique ? cmul(cmul(ph, pc), a.phy[ib * a.ny + y]) : cmul(ph, pc);
+    const float2* phxb = a.phx + ib * a.nx;
     sfor<0, N2>([&](auto M) {
       const int x = t + N1 * CV(M);
       float2 e;
@@ -421,7 +449,8 @@ k1_xpass(CbsArgs a) {
         w = cmul(make_float2(v0.x, v0.y - a.eps), e);
         if (a.src == SRC_PLANE) {
           const bool xin = (x >= a.px) && (x < a.nx - a.px);
-          if (xin && yin && zin) w = cadd(w, cmul(v0, spl));
+          if (xin && yin && zin)
+            w = cadd(w, cmul(v0, a.oblique ? cmul(spl, phxb[x]) : spl));
         } else if (a.src == SRC_FIELD) {
           w = cadd(w, cscale(a.fin[ebase + x], a.src_scale));
         } else if (a.src == SRC_FIELD_CONJ) {
@@ -447,7 +476,8 @@ k1_xpass(CbsArgs a) {
     sfor<0, N1>([&](auto K) { wat(t + N2 * CV(K)) = bo[CV(K)]; });
   }
   if constexpr (MODE == K1_ITER) {
-    block_sum2<G::THREADS>(sd, se, red, a.partials + 2 * (long long)blockIdx.x);
+    const long long slot = (long long)ib * a.k1_blocks + (long long)rest * 3 + c;
+    block_sum2<G::THREADS>(sd, se, red, a.partials + 2 * slot);
     if (blockIdx.x == 0 && threadIdx.x == 0) a.st->pending = 1;
   }
 }
@@ -470,11 +500,11 @@ ky_pass(CbsArgs a) {
     // wrote the partials has completed); lds is still unused here
     constexpr bool kFits = sizeof(lds) >= 2 * kResStreams * sizeof(double);
     if constexpr (kFits) {
-      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist,
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.nb, a.st, a.hist,
                                   reinterpret_cast<double*>(lds));
     } else {
       __shared__ double red[2 * kResStreams];
-      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.st, a.hist, red);
+      residual_finish<G::THREADS>(a.partials, a.k1_blocks, a.nb, a.st, a.hist, red);
     }
     if (tid == 0) a.st->pending = 0;
     __syncthreads();
@@ -484,7 +514,8 @@ ky_pass(CbsArgs a) {
   const int xi = tid % TX;
   const int t = tid / TX;
   const unsigned gx = (unsigned)(a.nx + TX - 1) / TX;
-  const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.nz * 3u);
+  // component c < 3 nb: the W fields of a batch follow each other (sWb = 3 sW)
+  const unsigned L = xcd_remap(blockIdx.x, gx * (unsigned)a.nz * 3u * (unsigned)a.nb);
   const int bx = (int)(L % gx);
   const unsigned rest = L / gx;
   const int z = (int)(rest % (unsigned)a.nz), c = (int)(rest / (unsigned)a.nz);
@@ -551,7 +582,10 @@ kz_pass(CbsArgs a) {
   // brick; rows y, y+1 of a brick share a 128-byte line
   static_assert(kBrick % TX == 0, "z-pass tiles split a brick row evenly");
   constexpr int PARTS = kBrick / TX;
-  const unsigned L = xcd_remap(blockIdx.x, (unsigned)(a.nxp / TX) * (unsigned)a.ny);
+  const unsigned per_b = (unsigned)(a.nxp / TX) * (unsigned)a.ny;
+  const unsigned Lb = xcd_remap(blockIdx.x, per_b * (unsigned)a.nb);
+  const int ib = (int)(Lb / per_b);
+  const unsigned L = Lb - (unsigned)ib * per_b;
   const int part = (int)(L % PARTS);
   const int y = (int)((L / PARTS) % (unsigned)a.ny);
   const int brick = (int)(L / (PARTS * (unsigned)a.ny));
@@ -559,7 +593,7 @@ kz_pass(CbsArgs a) {
   const int x = bx * TX + xi;
   const bool xok = x < a.nx;
   const long long plane = (long long)a.ny * a.nxp;   // z stride (gx bricks of ny x 8)
-  float2* colbase = a.W + ((long long)brick * a.ny + y) * kBrick + part * TX + xi;
+  float2* colbase = a.W + ib * a.sWb + ((long long)brick * a.ny + y) * kBrick + part * TX + xi;
 
   const long long zst = (long long)N2 * plane;  // z stride between the samples of one DFT-N1
   // forward level A: thread (c, j2), DFT-N1 over z = j2 + N2 j1
@@ -742,7 +776,7 @@ void launch_k1(const CbsArgs& a_in, int mode, hipStream_t s) {
   using G = XGeom<N1, N2>;
   CbsArgs a = a_in;
   a.k1_prio = k1_low_occupancy<N1, N2>();
-  const unsigned nb = 3u * (unsigned)a.gy * (unsigned)a.nz;
+  const unsigned nb = 3u * (unsigned)a.nb * (unsigned)a.gy * (unsigned)a.nz;
   if (mode == K1_FWD)
     hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD>), dim3(nb), dim3(G::THREADS), 0, s, a);
   else if (mode == K1_ITER)
@@ -771,7 +805,7 @@ void launch_ky(const CbsArgs& a_in, int sign, hipStream_t s) {
   using G = YGeom<N1, N2, kTY>;
   CbsArgs a = a_in;
   a.ky_prio = ky_low_occupancy<N1, N2>();
-  dim3 grid((unsigned)((long long)((a.nx + kTY - 1) / kTY) * a.nz * 3));
+  dim3 grid((unsigned)((long long)((a.nx + kTY - 1) / kTY) * a.nz * 3 * a.nb));
   if (sign < 0)
     hipLaunchKernelGGL((ky_pass<N1, N2, kTY, -1>), grid, dim3(G::THREADS), 0, s, a);
   else
@@ -782,7 +816,7 @@ template <int N1, int N2>
 void launch_kz(const CbsArgs& a, hipStream_t s) {
   constexpr int TX = kz_tx_for(N1, N2);
   using G = ZGeom<N1, N2, TX>;
-  dim3 grid((unsigned)((long long)(a.nxp / TX) * a.ny));
+  dim3 grid((unsigned)((long long)(a.nxp / TX) * a.ny * a.nb));
   hipLaunchKernelGGL((kz_pass<N1, N2, TX>), grid, dim3(G::THREADS), 0, s, a);
 }
 

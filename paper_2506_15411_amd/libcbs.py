@@ -57,7 +57,7 @@ class cbs_lens_figures(ctypes.Structure):
 class cbs_source(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("pol", (ctypes.c_double * 2) * 3),
                 ("field", ctypes.c_void_p), ("r0", ctypes.c_int * 3),
-                ("amp", (ctypes.c_double * 2) * 3)]
+                ("amp", (ctypes.c_double * 2) * 3), ("dir", ctypes.c_double * 2)]
 
 
 class CbsError(RuntimeError):
@@ -73,8 +73,12 @@ SYMBOLS = [
     "cbs_plan_set_pml_profile", "cbs_plan_set_shift_factor", "cbs_set_permittivity", "cbs_solve", "cbs_adjoint_solve",
     "cbs_solve_begin", "cbs_solve_advance", "cbs_solve_poll", "cbs_solve_end", "cbs_batch_step",
     "cbs_gradient", "cbs_lens_metrics", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
-    "cbs_last_error",
+    "cbs_last_error", "cbs_batch_workspace_bytes", "cbs_solve_batch",
+    "cbs_tfsf_source",
 ]
+
+CBS_MAX_ILLUMINATIONS = 8
+
 
 
 def load(path: str | None = None):
@@ -135,6 +139,13 @@ def load(path: str | None = None):
     lib.cbs_eps_shift.restype = c_double
     lib.cbs_plan_destroy.argtypes = [c_void_p]
     lib.cbs_plan_destroy.restype = c_int
+    lib.cbs_batch_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int]
+    lib.cbs_batch_workspace_bytes.restype = c_size_t
+    lib.cbs_solve_batch.argtypes = [c_void_p, c_int, P(cbs_source), c_void_p, P(cbs_opts),
+                                    P(cbs_stats), c_void_p, c_size_t]
+    lib.cbs_solve_batch.restype = c_int
+    lib.cbs_tfsf_source.argtypes = [c_void_p, P(cbs_source), P(c_int), P(c_int), c_void_p]
+    lib.cbs_tfsf_source.restype = c_int
     lib.cbs_last_error.argtypes = []
     lib.cbs_last_error.restype = ctypes.c_char_p
     if path is None:
@@ -278,6 +289,25 @@ def cbs_eps_shift(plan) -> float:
 
 def cbs_plan_destroy(plan):
     return check(load().cbs_plan_destroy(plan))
+
+
+def cbs_batch_workspace_bytes(nx, ny, nz, count) -> int:
+    return int(load().cbs_batch_workspace_bytes(nx, ny, nz, count))
+
+
+def cbs_solve_batch(plan, srcs, E_ptr, opts: cbs_opts, work_ptr, work_bytes):
+    n = len(srcs)
+    arr = (cbs_source * n)(*srcs)
+    st = (cbs_stats * n)()
+    rc = load().cbs_solve_batch(plan, n, arr, ctypes.c_void_p(E_ptr), ctypes.byref(opts), st,
+                                ctypes.c_void_p(work_ptr), work_bytes)
+    check(rc, allow_not_converged=True)
+    return rc, [st[i] for i in range(n)]
+
+
+def cbs_tfsf_source(plan, src: cbs_source | None, lo, hi, S_ptr):
+    return check(load().cbs_tfsf_source(plan, ctypes.byref(src) if src is not None else None,
+                                        _ints3(lo), _ints3(hi), ctypes.c_void_p(S_ptr)))
 
 
 def cbs_last_error() -> str:

@@ -102,7 +102,7 @@ class Plan:
             | (L.CBS_RECORD_HISTORY if history else 0)
         return L.cbs_opts(float(tol), int(max_iter), int(check_every), flags)
 
-    def _forward_source(self, pol=None, field=None, point=None, kind=None):
+    def _forward_source(self, pol=None, field=None, point=None, kind=None, direction=None):
         src = L.cbs_source()
         if field is not None:
             _require_gpu(field, "field", torch.complex64, self.fshape)
@@ -123,6 +123,8 @@ class Plan:
                 for c in range(3):
                     a = complex(pol[c])
                     src.pol[c][0], src.pol[c][1] = a.real, a.imag
+            if direction is not None:
+                src.dir[0], src.dir[1] = float(direction[0]), float(direction[1])
         return src
 
     def _adjoint_source(self, E_fwd=None, r0=None, amp=None, field=None, conj=False):
@@ -150,12 +152,13 @@ class Plan:
 
     def solve(self, E: torch.Tensor | None = None, tol=1e-4, max_iter=20000, check_every=10,
               warm=False, scattered=False, history=False, pol=None, field=None, point=None,
-              kind=None):
-        """Forward solve (plane wave by default).  Returns (E, SolveStats)."""
+              kind=None, direction=None):
+        """Forward solve (plane wave by default: x-polarised, normal incidence;
+        direction = (kx, ky) / kb tilts it).  Returns (E, SolveStats)."""
         if E is None:
             E = self.new_field()
         _require_gpu(E, "E", torch.complex64, self.fshape)
-        src = self._forward_source(pol, field, point, kind)
+        src = self._forward_source(pol, field, point, kind, direction)
         self._src_keep = src
         rc, st = L.cbs_solve(self.handle, src, E.data_ptr(),
                              self._opts(tol, max_iter, check_every, warm, scattered, history))
@@ -175,6 +178,32 @@ class Plan:
         rc, st = L.cbs_adjoint_solve(self.handle, fptr, src, E_adj.data_ptr(),
                                      self._opts(tol, max_iter, check_every, warm, False, history))
         return E_adj, _stats(rc, st)
+
+    def solve_batch(self, illuminations, E: torch.Tensor | None = None, tol=1e-4,
+                    max_iter=20000, check_every=10, warm=False, scattered=False,
+                    history=False):
+        """Several plane-wave illuminations of the current medium in one batched
+        solve (see cbs_solve_batch).  illuminations: list of (pol, direction)
+        pairs (None for x-polarised / normal incidence).  Returns
+        (E [count, 3, nz, ny, nx], [SolveStats per illumination])."""
+        n = len(illuminations)
+        shape = (n,) + self.fshape
+        if E is None:
+            with torch.cuda.stream(self.stream):
+                E = torch.zeros(shape, dtype=torch.complex64, device=self.device)
+        _require_gpu(E, "E", torch.complex64, shape)
+        srcs = [self._forward_source(pol, None, None, None, d) for pol, d in illuminations]
+        nbytes = L.cbs_batch_workspace_bytes(*self.shape, n)
+        if nbytes == 0:
+            raise ValueError(f"{n} illuminations: 1..{L.CBS_MAX_ILLUMINATIONS} supported")
+        with torch.cuda.stream(self.stream):
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        rc, sts = L.cbs_solve_batch(self.handle, srcs, E.data_ptr(),
+                                    self._opts(tol, max_iter, check_every, warm, scattered,
+                                               history),
+                                    raw.data_ptr() + off, nbytes)
+        return E, [_stats(rc, st) for st in sts]
 
     # -- asynchronous solves (one at a time per plan; plans overlap) ---------
     def begin(self, E: torch.Tensor, adjoint=False, E_fwd=None, r0=None, amp=None, field=None,
@@ -224,6 +253,16 @@ class Plan:
             out = torch.empty(bshape, dtype=torch.float32, device=self.device)
         _require_gpu(out, "out", torch.float32, bshape)
         L.cbs_gradient(self.handle, E.data_ptr(), E_adj.data_ptr(), lo, hi, scale, out.data_ptr())
+        return out
+
+    def tfsf_source(self, lo, hi, pol=None, direction=None, out: torch.Tensor | None = None):
+        """Total-field / scattered-field source of a plane wave for the box
+        [lo, hi) (see cbs_tfsf_source); solve it with solve(field=...)."""
+        if out is None:
+            out = self.new_field()
+        _require_gpu(out, "out", torch.complex64, self.fshape)
+        src = self._forward_source(pol, None, None, None, direction)
+        L.cbs_tfsf_source(self.handle, src, lo, hi, out.data_ptr())
         return out
 
     def apply_green(self, W: torch.Tensor, out: torch.Tensor | None = None):

@@ -12,6 +12,9 @@ from paper_2506_15411_amd.solver import Plan
 
 pytestmark = pytest.mark.gpu
 LAM = 1.064e-6
+# the FP32 iteration's residual floor on these 16 x 14 x 18 grids is about
+# 1.5e-7; solves to 5e-7 are converged and stop there
+TOL = 5e-7
 
 
 def rel(a, b):
@@ -29,7 +32,7 @@ def test_focal_intensity_gradient_matches_oracle(device):
     g, p, eps = setup(device)
     r0 = (8, 7, 12)
     e = torch.from_numpy(eps).to(device).requires_grad_(True)
-    L = focal_intensity(e, p, r0, tol=1e-7, max_iter=5000)
+    L = focal_intensity(e, p, r0, tol=TOL, max_iter=5000)
     L.backward()
     Eo, _ = oc.solve_forward(g, eps, tol=1e-11, max_iter=40000)
     ga = oc.solve_adjoint(g, eps, oc.adjoint_point_source(g, Eo, r0), tol=1e-11, max_iter=40000)
@@ -37,8 +40,8 @@ def test_focal_intensity_gradient_matches_oracle(device):
     assert L.item() == pytest.approx(oc.focal_objective(Eo, r0), rel=1e-4)
     assert rel(e.grad.cpu().numpy(), gref) < 1e-3
     # the point-source adjoint path gives the same gradient
-    E, _ = p.solve(tol=1e-7, max_iter=5000)
-    Ea, _ = p.adjoint(E_fwd=E, r0=r0, tol=1e-7, max_iter=5000)
+    E, _ = p.solve(tol=TOL, max_iter=5000)
+    Ea, _ = p.adjoint(E_fwd=E, r0=r0, tol=TOL, max_iter=5000)
     gp = p.gradient(E, Ea, scale=2.0)
     assert rel(e.grad.cpu().numpy(), gp.cpu().numpy()) < 1e-4
 
@@ -46,7 +49,7 @@ def test_focal_intensity_gradient_matches_oracle(device):
 def test_general_loss_gradient_matches_oracle(device):
     g, p, eps = setup(device, seed=29)
     e = torch.from_numpy(eps).to(device).requires_grad_(True)
-    E = cbs_solve(e, p, tol=1e-7, max_iter=5000)
+    E = cbs_solve(e, p, tol=TOL, max_iter=5000)
     region = (slice(None), slice(9, 14), slice(5, 9), slice(6, 10))
     L = (E[region].abs() ** 2).sum() + E[0, 12, 7, 8].real - 0.5 * E[2, 11, 6, 9].imag
     L.backward()
@@ -63,11 +66,13 @@ def test_general_loss_gradient_matches_oracle(device):
 def test_directional_finite_difference(device):
     """GPU-only check: (L(eps + h v) - L(eps - h v)) / 2h against <grad, v> for
     the coherent direction v = sign(grad) over the interior, with h chosen so
-    that L moves by about 1% (FP32 solves to tol 1e-8)."""
+    that L moves by about 1%.  The solves iterate to the FP32 floor of the
+    residual (about 1.6e-7 on this grid: tol 1e-8 is not reached, so the
+    20000-iteration cap ends them and strict is off)."""
     g, p, eps = setup(device, seed=31)
     r0 = (8, 7, 12)
     e = torch.from_numpy(eps).to(device).requires_grad_(True)
-    L = focal_intensity(e, p, r0, tol=1e-8, max_iter=20000)
+    L = focal_intensity(e, p, r0, tol=1e-8, max_iter=20000, strict=False)
     L.backward()
     mask = torch.zeros_like(e)
     mask[3:-3, 2:-2, 2:-2] = 1.0
@@ -75,8 +80,8 @@ def test_directional_finite_difference(device):
     dg = float((e.grad * vt).sum().item())
     h = 0.01 * L.item() / dg
     with torch.no_grad():
-        Lp = focal_intensity(e + h * vt, p, r0, tol=1e-8, max_iter=20000).item()
-        Lm = focal_intensity(e - h * vt, p, r0, tol=1e-8, max_iter=20000).item()
+        Lp = focal_intensity(e + h * vt, p, r0, tol=1e-8, max_iter=20000, strict=False).item()
+        Lm = focal_intensity(e - h * vt, p, r0, tol=1e-8, max_iter=20000, strict=False).item()
     fd = (Lp - Lm) / (2 * h)
     assert abs(fd - dg) <= 1e-3 * abs(dg)
 

@@ -65,8 +65,8 @@ def test_lens16_converged_field_vs_fp64_fixture(device):
     assert p.eps_shift == pytest.approx(float(gd["eps_shift"]), rel=1e-12)
     E, st = p.solve(tol=1e-6, max_iter=20000, scattered=True)
     assert st.status == L.CBS_OK
-    print(f"GPU {st.iterations} iterations to {st.residual:.2e}; oracle "
-          f"{int(gd['iterations'])} to {float(gd['eta']):.2e}")
+    print(f"GPU {st.iterations} iterations to {st.residual:.2e}; FP64 solution's own "
+          f"eta {float(gd['eta']):.2e}")
     x0, y0, z0 = sc.r0
     check_samples(E[:, z0].cpu().numpy(), gd["focal_plane"], "focal plane")
     check_samples(E[:, :, y0, :].cpu().numpy(), gd["xz_plane"], "xz plane")
@@ -87,8 +87,8 @@ def test_lens16_converged_gradient_vs_fp64_fixture(device):
     E, s1 = p.solve(tol=1e-6, max_iter=20000)
     Ea, s2 = p.adjoint(E_fwd=E, r0=sc.r0, tol=1e-6, max_iter=20000)
     assert s1.status == L.CBS_OK and s2.status == L.CBS_OK
-    print(f"GPU {s1.iterations} + {s2.iterations} iterations; oracle "
-          f"{list(gd['iterations'])}")
+    print(f"GPU {s1.iterations} + {s2.iterations} iterations; FP64 solutions' own eta "
+          f"{list(gd['eta'])}")
     x0, y0, z0 = sc.r0
     fom = float((E[:, z0, y0, x0].abs() ** 2).sum().item())
     assert fom == pytest.approx(float(gd["objective"]), rel=1e-3)
@@ -118,8 +118,8 @@ def test_sphere64_gradient_vs_fp64_central_differences(device):
     assert tuple(gd["r0"]) == r0 and tuple(gd["box_lo"]) == lo and tuple(gd["box_hi"]) == hi
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(eps).to(device))
-    E, s1 = p.solve(tol=1e-7, max_iter=20000)
-    Ea, s2 = p.adjoint(E_fwd=E, r0=r0, tol=1e-7, max_iter=20000)
+    E, s1 = p.solve(tol=5e-7, max_iter=20000)
+    Ea, s2 = p.adjoint(E_fwd=E, r0=r0, tol=5e-7, max_iter=20000)
     assert s1.status == L.CBS_OK and s2.status == L.CBS_OK
     grad = p.gradient(E, Ea, lo, hi, scale=2.0).double().cpu().numpy()
     worst = 0.0
@@ -134,17 +134,18 @@ def test_sphere64_gradient_vs_fp64_central_differences(device):
 
 def test_lens16_slab_random_direction_difference(device):
     """Directional difference of |E(r0)|^2 along a random +-1 direction over the
-    whole 2 um slab of the 16 um lens (h = 1e-2), GPU solves to tol 1e-7, against
-    <grad, v>.  The FP32 noise floor of the objective is measured as the spread
-    of |E(r0)|^2 over solves started from different fields; the difference must
-    agree with <grad, v> within the floor's effect plus 2% (second-order terms
-    of the central difference)."""
+    whole 2 um slab of the 16 um lens (h = 1e-2), GPU solves to tol 1e-6 (the
+    FP32 residual floor of this volume is about 5e-7), against <grad, v>.  The
+    FP32 noise floor of the objective is measured as the spread of |E(r0)|^2
+    over solves started from different fields; the difference must agree with
+    <grad, v> within the floor's effect plus 2% (second-order terms of the
+    central difference)."""
     sc = scenes.zoneplate16_design(0)
     lo, hi = sc.design_box
     x0, y0, z0 = sc.r0
     eps = torch.from_numpy(sc.eps_r).to(device)
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
-    tol = 1e-7
+    tol = 1e-6
 
     def fom(e, warm=None):
         p.set_permittivity(e)

@@ -101,36 +101,56 @@ def test_design_volume_single_modes_closed_form(device):
     p.close()
 
 
-def test_design_volume_lens_twenty_iterations_vs_oracle(device):
+# The FP64 oracle takes several seconds per iteration at these sizes, so a long
+# equal-iteration comparison is split into consecutive tests (each ends well
+# inside a few minutes): the oracle's field is kept between them and every test
+# continues the same iteration (the CBS step depends only on the current field;
+# a test run alone starts from zero).  The GPU runs each count from zero.
+_ORACLE_STATE = {}
+
+
+def oracle_iterate(key, g, eps, S, upto):
+    k, E = _ORACLE_STATE.get(key, (0, None))
+    if k > upto:
+        k, E = 0, None
+    res = oc.cbs(g, eps, S, tol=0.0, max_iter=upto - k, E0=E) if upto > k else None
+    E = res.E_s if res is not None else E
+    _ORACLE_STATE[key] = (upto, E)
+    return E, (res.history if res is not None else [])
+
+
+@pytest.mark.parametrize("upto", [10, 20])
+def test_design_volume_lens_iterations_vs_oracle(upto, device):
     """The benchmarked volume and medium (100 um lens with its design slab):
-    20 CBS iterations on the GPU and in the FP64 oracle, whole volume."""
+    10 and 20 CBS iterations on the GPU and in the FP64 oracle, whole volume,
+    and the residual of every iteration."""
     sc = scenes.zoneplate100_design(0)
-    k = 20
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
-    E, st = p.solve(tol=0.0, max_iter=k, scattered=True, history=True)
+    E, st = p.solve(tol=0.0, max_iter=upto, scattered=True, history=True)
     hist = np.array(p.history())
+    assert st.iterations == upto
     g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
-    res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=k)
-    err = rel_chunked(E, res.E_s)
-    print(f"621x621x261, {k} iterations: rel-L2 {err:.2e}, eta {st.residual:.4e} vs {res.eta:.4e}")
-    assert st.iterations == k
-    assert np.all(np.abs(hist - np.array(res.history)) <= 1e-4 * np.array(res.history))
+    Eo, h = oracle_iterate("zoneplate100", g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), upto)
+    err = rel_chunked(E, Eo)
+    h = np.array(h)
+    print(f"621x621x261, {upto} iterations: rel-L2 {err:.2e}, eta {st.residual:.4e}")
+    assert np.all(np.abs(hist[len(hist) - len(h):] - h) <= 1e-4 * h)
     assert err < 1e-4
     p.close()
 
 
-def test_lens16_hundred_iterations_vs_oracle(device):
-    """The 16 um lens of the Fig. 1 benchmark: 100 iterations, whole volume."""
+@pytest.mark.parametrize("upto", [25, 50, 75, 100])
+def test_lens16_iterations_vs_oracle(upto, device):
+    """The 16 um lens of the Fig. 1 benchmark: up to 100 iterations, whole volume."""
     sc = scenes.zoneplate16()
     p = Plan(sc.shape, sc.pitch, LAM, 1.0, sc.pml, device=device)
     p.set_permittivity(torch.from_numpy(sc.eps_r).to(device))
-    k = 100
-    E, st = p.solve(tol=0.0, max_iter=k, scattered=True)
+    E, st = p.solve(tol=0.0, max_iter=upto, scattered=True)
     g = oc.Grid(*sc.shape, sc.pitch, LAM, 1.0, sc.pml)
-    res = oc.cbs(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), tol=0.0, max_iter=k)
-    err = rel_chunked(E, res.E_s)
-    print(f"275x275x315, {k} iterations: rel-L2 {err:.2e}")
+    Eo, _ = oracle_iterate("zoneplate16", g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r), upto)
+    err = rel_chunked(E, Eo)
+    print(f"275x275x315, {upto} iterations: rel-L2 {err:.2e}")
     assert err < 1e-4
     p.close()
 
