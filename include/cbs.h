@@ -315,6 +315,30 @@ int cbs_time_passes(cbs_plan_t plan, void* E_dev, int iters, float* ms_out);
 int cbs_bandwidth_probe(const void* src_dev, void* dst_dev, size_t bytes, int reps,
                         void* stream, float* ms_out);
 
+/* ---- allocation-free solve ----------------------------------------------
+ * For callers that cannot allocate device memory or create HIP objects (code
+ * under stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the forward solve of cbs_plan_create + cbs_set_permittivity + cbs_solve in
+ * one call that allocates nothing (no hipMalloc, hipFree, host-pinned memory,
+ * events or other allocating routine).  Its scratch -- the workspace a plan of
+ * this grid would take: spectral work field, potential, tables, partial sums,
+ * solve state -- is one static device array of CBS_STATIC_SCRATCH_BYTES, which
+ * each GPU the library runs on holds until the process ends.
+ *   nx .. pml        as cbs_plan_create (default absorbing profile, shift 1.1)
+ *   eps_r_dev, dtype as cbs_set_permittivity (same validation)
+ *   src .. stats     as cbs_solve; stats->ms is host wall time of the solve
+ *   stream           hipStream_t the work is ordered on (NULL = default stream)
+ * Returns CBS_E_WORKSPACE, before any device work, for a grid whose workspace
+ * (cbs_plan_workspace_bytes) exceeds CBS_STATIC_SCRATCH_BYTES (64^3 and 128^3
+ * fit; the 275 x 275 x 315 lens does not).  Synchronises the stream; the field
+ * is complete on return.  Every call on a GPU uses that GPU's one array: calls
+ * that overlap on one GPU (other host threads, other streams) race and must be
+ * serialised by the caller.  Nothing an earlier call left in the array is read. */
+#define CBS_STATIC_SCRATCH_BYTES ((size_t)96 << 20)
+int cbs_solve_static(int nx, int ny, int nz, double pitch_m, double lambda0_m, double n_bg,
+                     const int pml[3], const void* eps_r_dev, int dtype, const cbs_source* src,
+                     void* E_dev, const cbs_opts* opts, cbs_stats* stats, void* stream);
+
 /* eps (1/m^2) of the current medium, or a negative value if none is set. */
 double cbs_eps_shift(cbs_plan_t plan);
 

@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <chrono>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -623,6 +625,13 @@ struct cbs_plan_s {
   DevState last;     // state read at the last completed quantum
 };
 
+// The workspace of cbs_solve_static: one plan's scratch in a static device
+// array, held by each GPU the library runs on until the process ends.  In host
+// code cbs_scratch names a host-side stand-in; its device address comes from
+// hipGetSymbolAddress, once per device (static_scratch below), and only that
+// address is ever passed to a kernel or a copy.
+static __device__ __align__(256) unsigned char cbs_scratch[CBS_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 struct Layout {
@@ -1127,10 +1136,108 @@ int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cb
   return CBS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free solve: the workspace of one plan in a static device array
+// ---------------------------------------------------------------------------
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];   // device address of cbs_scratch, per device
+
+int static_scratch(void** out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(CBS_E_HIP, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(cbs_scratch)));
+    if (!ptr || reinterpret_cast<uintptr_t>(ptr) % 256 != 0)
+      return fail(CBS_E_HIP, "static scratch of device %d has no usable address", dev);
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return CBS_OK;
+}
+
+__global__ void k_clear_words(unsigned* w, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) w[i] = 0u;
+}
+
+// The blocking solve loop without events or a pinned ring: enqueue
+// check_every iterations and the residual, read the device state back
+// synchronously, repeat until the device has stopped.
+int run_static(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_source* src,
+               const Kvec& kv, cbs_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (int rc = enqueue_solve_start(p, a, o, src, nullptr, kv)) return rc;
+  p->ox->k1(a, K1_FWD, p->stream);
+  HIP_LAUNCHED();
+  DevState hs;
+  std::memset(&hs, 0, sizeof(hs));
+  int enqueued = 0;
+  for (;;) {
+    const int q = std::min(o->check_every, o->max_iter - enqueued);
+    for (int i = 0; i < q; ++i)
+      if (int rc = enqueue_iteration(p, a)) return rc;
+    enqueued += q;
+    if (int rc = enqueue_residual(p, a)) return rc;
+    HIP_TRY(hipMemcpyAsync(&hs, p->state, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
+    HIP_TRY(hipStreamSynchronize(p->stream));
+    if (hs.done || enqueued >= o->max_iter) break;
+  }
+  if (a.src == SRC_PLANE && !(o->flags & CBS_RETURN_SCATTERED)) {
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, a, 1.0f);
+    HIP_LAUNCHED();
+  }
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) {
+    stats->iterations = hs.iter;
+    stats->converged = hs.status == 1;
+    stats->residual = hs.eta;
+    stats->eps_shift = p->eps;
+    stats->ms = (float)ms;
+  }
+  if (hs.status == 3) return fail(CBS_E_DIVERGED, "non-finite residual after %d iterations", hs.iter);
+  if (hs.status == 1) return CBS_OK;
+  g_err = "max_iter reached before the residual met tol";
+  return CBS_NOT_CONVERGED;
+}
+
 }  // namespace
 
 extern "C" {
 
+int cbs_solve_static(int nx, int ny, int nz, double pitch_m, double lambda0_m, double n_bg,
+                     const int pml[3], const void* eps_r_dev, int dtype, const cbs_source* src,
+                     void* E_dev, const cbs_opts* opts, cbs_stats* stats, void* stream) {
+  int pm[3];
+  if (int rc = check_grid(nx, ny, nz, pitch_m, lambda0_m, n_bg, pml, pm)) return rc;
+  Layout L;
+  layout_of(nx, ny, nz, L);
+  if (L.total > CBS_STATIC_SCRATCH_BYTES)
+    return fail(CBS_E_WORKSPACE,
+                "grid %dx%dx%d needs %zu bytes of scratch; the static scratch holds %zu "
+                "(use cbs_plan_create with a workspace)",
+                nx, ny, nz, L.total, (size_t)CBS_STATIC_SCRATCH_BYTES);
+  if (int rc = check_opts(opts)) return rc;
+  if (!eps_r_dev || !E_dev) return fail(CBS_E_INVALID, "eps_r or the output field is NULL");
+  void* base = nullptr;
+  if (int rc = static_scratch(&base)) return rc;
+  cbs_plan_s p{};   // on the stack: no events, no pinned memory
+  init_plan(&p, nx, ny, nz, pitch_m, lambda0_m, n_bg, pm, base, static_cast<hipStream_t>(stream));
+  Tables t;         // host staging of the tables, consumed before set-up returns
+  HIP_TRY(upload_tables(&p, t));
+  hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, p.stream,
+                     reinterpret_cast<unsigned*>(p.state), (int)(sizeof(DevState) / 4));
+  HIP_LAUNCHED();
+  if (int rc = set_permittivity_impl(&p, eps_r_dev, dtype)) return rc;   // synchronises
+  CbsArgs a;
+  Kvec kv;
+  if (int rc = prepare(&p, 0, src, E_dev, opts, a, kv)) return rc;
+  return run_static(&p, a, opts, src, kv, stats);
+}
 
 
 size_t cbs_plan_workspace_bytes(int nx, int ny, int nz) {

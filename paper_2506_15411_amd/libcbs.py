@@ -73,12 +73,13 @@ SYMBOLS = [
     "cbs_plan_set_pml_profile", "cbs_plan_set_shift_factor", "cbs_set_permittivity", "cbs_solve", "cbs_adjoint_solve",
     "cbs_solve_begin", "cbs_solve_advance", "cbs_solve_poll", "cbs_solve_end", "cbs_batch_step",
     "cbs_gradient", "cbs_lens_metrics", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
-    "cbs_last_error", "cbs_batch_workspace_bytes", "cbs_solve_batch",
+    "cbs_last_error", "cbs_solve_static", "cbs_batch_workspace_bytes", "cbs_solve_batch",
     "cbs_tfsf_source",
 ]
 
 CBS_MAX_ILLUMINATIONS = 8
 
+CBS_STATIC_SCRATCH_BYTES = 96 << 20
 
 
 def load(path: str | None = None):
@@ -139,6 +140,10 @@ def load(path: str | None = None):
     lib.cbs_eps_shift.restype = c_double
     lib.cbs_plan_destroy.argtypes = [c_void_p]
     lib.cbs_plan_destroy.restype = c_int
+    lib.cbs_solve_static.argtypes = [c_int, c_int, c_int, c_double, c_double, c_double, P(c_int),
+                                     c_void_p, c_int, P(cbs_source), c_void_p, P(cbs_opts),
+                                     P(cbs_stats), c_void_p]
+    lib.cbs_solve_static.restype = c_int
     lib.cbs_batch_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int]
     lib.cbs_batch_workspace_bytes.restype = c_size_t
     lib.cbs_solve_batch.argtypes = [c_void_p, c_int, P(cbs_source), c_void_p, P(cbs_opts),
@@ -289,6 +294,18 @@ def cbs_eps_shift(plan) -> float:
 
 def cbs_plan_destroy(plan):
     return check(load().cbs_plan_destroy(plan))
+
+
+def cbs_solve_static(nx, ny, nz, pitch, lambda0, n_bg, pml, eps_ptr, dtype,
+                     src: cbs_source | None, E_ptr, opts: cbs_opts, stream_ptr):
+    st = cbs_stats()
+    rc = load().cbs_solve_static(nx, ny, nz, pitch, lambda0, n_bg, _ints3(pml),
+                                 ctypes.c_void_p(eps_ptr), dtype,
+                                 ctypes.byref(src) if src is not None else None,
+                                 ctypes.c_void_p(E_ptr), ctypes.byref(opts), ctypes.byref(st),
+                                 ctypes.c_void_p(stream_ptr))
+    check(rc, allow_not_converged=True)
+    return rc, st
 
 
 def cbs_batch_workspace_bytes(nx, ny, nz, count) -> int:

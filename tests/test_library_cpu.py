@@ -88,3 +88,20 @@ def test_calls_on_null_plan_fail(lib):
     assert lib.cbs_solve(None, None, None, None, None) == L.CBS_E_INVALID
     assert lib.cbs_eps_shift(None) < 0
     assert lib.cbs_plan_destroy(None) == L.CBS_OK
+
+
+def test_static_solve_checks_before_any_device_call(lib):
+    """cbs_solve_static validates the grid and its scratch size on the host."""
+    hdr = open(os.path.join(ROOT, "include", "cbs.h")).read()
+    m = re.search(r"#define CBS_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and int(m.group(1)) << int(m.group(2)) == L.CBS_STATIC_SCRATCH_BYTES
+    opts = L.cbs_opts(1e-4, 10, 10, 0)
+    st = L.cbs_stats()
+    pml = (ctypes.c_int * 3)(8, 8, 48)
+    rc = lib.cbs_solve_static(275, 275, 315, 66.5e-9, 1.064e-6, 1.0, pml, None, 0, None, None,
+                              ctypes.byref(opts), ctypes.byref(st), None)
+    assert rc == L.CBS_E_WORKSPACE and b"static scratch" in lib.cbs_last_error()
+    rc = lib.cbs_solve_static(37 * 41, 8, 8, 1e-7, 1e-6, 1.0, None, None, 0, None, None,
+                              ctypes.byref(opts), ctypes.byref(st), None)
+    assert rc == L.CBS_E_INVALID
+    assert L.cbs_plan_workspace_bytes(128, 128, 128) <= L.CBS_STATIC_SCRATCH_BYTES
