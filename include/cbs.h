@@ -204,7 +204,10 @@ int cbs_solve_end(cbs_plan_t plan, cbs_stats* stats);
  * small grids need a fraction of the launches.  Every illumination has its own
  * residual; the solve stops when the largest reaches tol (or at max_iter), so
  * all illuminations run the same number of iterations, and at equal iteration
- * counts each field is bit-identical to a cbs_solve of that source alone.
+ * counts each field equals a cbs_solve of that source alone (bit for bit when
+ * the batch's illuminations are all at normal incidence or all oblique; a
+ * normal-incidence wave batched with an oblique one runs the x pass compiled
+ * for oblique waves and agrees to FP32 rounding).
  *
  * Device bytes of the batch workspace for `count` illuminations (1..8): the
  * spectral work fields, residual partials and phase tables of the batch; 0 if

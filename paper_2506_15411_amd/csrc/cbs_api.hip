@@ -201,11 +201,12 @@ __global__ void k_incident(CbsArgs a, float sign) {
     const int y = (int)((i / a.nx) % a.ny);
     const int z = (int)(i / ((long long)a.nx * a.ny));
     for (int b = 0; b < a.nb; ++b) {
-      float2 ph = a.phase[b * a.nz + z];
-      if (a.oblique) ph = cmul(cmul(ph, a.phy[b * a.ny + y]), a.phx[b * a.nx + x]);
+      const float2 pxy = a.oblique ? cmul(a.phy[b * a.ny + y], a.phx[b * a.nx + x])
+                                   : make_float2(1.f, 0.f);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const float2 inc = cmul(ph, a.pol[b][c]);
+        const float2 pz = a.phase[(b * 3 + c) * a.nz + z];
+        const float2 inc = a.oblique ? cmul(pz, pxy) : pz;
         float2* ep = a.E + b * a.sEb + c * a.sE + i;
         float2 e = *ep;
         e.x += sign * inc.x;
@@ -216,26 +217,33 @@ __global__ void k_incident(CbsArgs a, float sign) {
   }
 }
 
-// Plane-wave phase tables of the illuminations of a solve, in FP64 rounded to
-// FP32: phx[b][x] = exp(i kx_b d x), phy[b][y] = exp(i ky_b d y),
-// phz[b][z] = exp(i kz_b d z); phase zero at the voxel (0, 0, 0).
+// Plane-wave tables of the illuminations of a solve, in FP64 rounded to FP32:
+// phx[b][x] = exp(i kx_b d x), phy[b][y] = exp(i ky_b d y) and
+// phz[b][c][z] = pol_{b,c} exp(i kz_b d z); phase zero at the voxel (0, 0, 0).
 struct Kvec {
   int nb;
-  double kd[kMaxIllum][3];   // (kx, ky, kz) d of each illumination
+  double kd[kMaxIllum][3];       // (kx, ky, kz) d of each illumination
+  double pol[kMaxIllum][3][2];   // polarisation (re, im)
 };
 __global__ void k_phase_tables(float2* phx, float2* phy, float2* phz, int nx, int ny, int nz,
                                Kvec kv) {
-  const int per = nx + ny + nz;
+  const int per = nx + ny + 3 * nz;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kv.nb * per; i += gridDim.x * blockDim.x) {
     const int b = i / per, j = i - b * per;
-    int axis, k;
-    float2* out;
-    if (j < nx) { axis = 0; k = j; out = phx + b * nx + k; }
-    else if (j < nx + ny) { axis = 1; k = j - nx; out = phy + b * ny + k; }
-    else { axis = 2; k = j - nx - ny; out = phz + b * nz + k; }
     double sn, cs;
-    sincos(kv.kd[b][axis] * (double)k, &sn, &cs);
-    *out = make_float2((float)cs, (float)sn);
+    if (j < nx) {
+      sincos(kv.kd[b][0] * (double)j, &sn, &cs);
+      phx[b * nx + j] = make_float2((float)cs, (float)sn);
+    } else if (j < nx + ny) {
+      const int k = j - nx;
+      sincos(kv.kd[b][1] * (double)k, &sn, &cs);
+      phy[b * ny + k] = make_float2((float)cs, (float)sn);
+    } else {
+      const int m = j - nx - ny, c = m / nz, k = m - c * nz;
+      sincos(kv.kd[b][2] * (double)k, &sn, &cs);
+      const double pr = kv.pol[b][c][0], pi = kv.pol[b][c][1];
+      phz[(b * 3 + c) * nz + k] = make_float2((float)(pr * cs - pi * sn), (float)(pr * sn + pi * cs));
+    }
   }
 }
 
@@ -659,7 +667,7 @@ bool layout_of(int nx, int ny, int nz, Layout& L) {
   L.twx = take((size_t)nx * c8);
   L.twy = take((size_t)ny * c8);
   L.twz = take((size_t)nz * c8);
-  L.phase = take((size_t)nz * c8);
+  L.phase = take((size_t)3 * nz * c8);
   L.phx = take((size_t)nx * c8);
   L.phy = take((size_t)ny * c8);
   L.partials = take((size_t)2 * k1b * sizeof(double));
@@ -855,7 +863,6 @@ CbsArgs base_args(cbs_plan_s* p) {
   a.pfz = (float)(2.0 * M_PI / p->nz);
   a.invN = (float)(1.0 / ((double)p->nx * p->ny * p->nz));
   a.src_scale = (float)d2;
-  a.pol[0][0] = make_float2(1.f, 0.f);
   return a;
 }
 
@@ -901,7 +908,7 @@ int enqueue_solve_start(cbs_plan_s* p, CbsArgs& a, const cbs_opts* o, const cbs_
                         const void* E_fwd, const Kvec& kv) {
   if (a.src == SRC_PLANE) {
     // the incident plane waves' phase tables (built before anything reads them)
-    const int n = kv.nb * (p->nx + p->ny + p->nz);
+    const int n = kv.nb * (p->nx + p->ny + 3 * p->nz);
     hipLaunchKernelGGL(k_phase_tables, dim3((n + 255) / 256), dim3(256), 0, p->stream,
                        const_cast<float2*>(a.phx), const_cast<float2*>(a.phy),
                        const_cast<float2*>(a.phase), p->nx, p->ny, p->nz, kv);
@@ -1057,15 +1064,17 @@ int prepare(cbs_plan_s* p, int adjoint, const cbs_source* src, void* E, const cb
 // Illumination b of a plane-wave source: polarisation (x if all zero) and the
 // wave vector from the transverse direction cosines (normal incidence if zero).
 int set_plane_wave(cbs_plan_s* p, CbsArgs& a, Kvec& kv, int b, const cbs_source* src) {
-  a.pol[b][0] = make_float2(1.f, 0.f);
-  a.pol[b][1] = a.pol[b][2] = make_float2(0.f, 0.f);
+  for (int c = 0; c < 3; ++c) kv.pol[b][c][0] = kv.pol[b][c][1] = 0.0;
+  kv.pol[b][0][0] = 1.0;
   double sx = 0.0, sy = 0.0;
   if (src) {
     bool any = false;
     for (int c = 0; c < 3; ++c) any |= (src->pol[c][0] != 0.0 || src->pol[c][1] != 0.0);
     if (any)
-      for (int c = 0; c < 3; ++c)
-        a.pol[b][c] = make_float2((float)src->pol[c][0], (float)src->pol[c][1]);
+      for (int c = 0; c < 3; ++c) {
+        kv.pol[b][c][0] = src->pol[c][0];
+        kv.pol[b][c][1] = src->pol[c][1];
+      }
     sx = src->dir[0];
     sy = src->dir[1];
   }
@@ -1082,9 +1091,8 @@ int set_plane_wave(cbs_plan_s* p, CbsArgs& a, Kvec& kv, int b, const cbs_source*
 int set_source(cbs_plan_s* p, CbsArgs& a, const cbs_source* src, bool adjoint, Kvec& kv) {
   const int kind = src ? src->kind : CBS_SRC_PLANE_WAVE;
   kv.nb = 1;
-  for (int c = 0; c < 3; ++c) kv.kd[0][c] = 0.0;
-  a.pol[0][0] = make_float2(1.f, 0.f);
-  a.pol[0][1] = a.pol[0][2] = make_float2(0.f, 0.f);
+  for (int c = 0; c < 3; ++c) kv.kd[0][c] = kv.pol[0][c][0] = kv.pol[0][c][1] = 0.0;
+  kv.pol[0][0][0] = 1.0;
   switch (kind) {
     case CBS_SRC_NONE:
       a.src = SRC_NONE;
@@ -1406,7 +1414,7 @@ bool batch_layout(int nx, int ny, int nz, int count, BatchLayout& B) {
   B.partials = take((size_t)count * 2 * k1b * sizeof(double));
   B.phx = take((size_t)count * nx * sizeof(float2));
   B.phy = take((size_t)count * ny * sizeof(float2));
-  B.phz = take((size_t)count * nz * sizeof(float2));
+  B.phz = take((size_t)count * 3 * nz * sizeof(float2));
   B.total = off;
   return true;
 }

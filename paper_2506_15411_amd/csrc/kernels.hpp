@@ -161,7 +161,7 @@ struct CbsArgs {
   const float2* twx;            // x split n1 x n2: twx[j2 n1 + k1] = exp(-2 pi i j2 k1 / nx)
   const float2* twy;            // same layout for the y split
   const float2* twz;            // same layout for the z split
-  const float2* phase;          // [nb][nz] exp(i kz d z) of each illumination's plane wave
+  const float2* phase;          // [nb][3][nz] pol_c exp(i kz d z) of each illumination's wave
   const float2* fin;            // FIELD source / Green input
   float2* fout;                 // Green output
   double* partials;             // 2 doubles per K1 block
@@ -179,7 +179,6 @@ struct CbsArgs {
   int warm;                     // K1_FWD: W = V E + S from E (else E = 0)
   int green_in;                 // K1_FWD: W = fin
   int r0x, r0y, r0z;
-  float2 pol[kMaxIllum][3];     // polarisation of each illumination's plane wave
   float src_scale;              // d^2: physical (1/m^2) sources and Green inputs
   float eps, inv_eps, kb2;      // eps d^2, 1/(eps d^2), kb^2 d^2
   float pfx, pfy, pfz;          // 2 pi / n_a
@@ -319,7 +318,9 @@ __device__ __forceinline__ void block_sum2(double a, double b, double* red, doub
 // sits at brick x/8, offset 8 y + x%8, so the R rows of one brick form one
 // contiguous 64 R-byte piece.  The inverse transform, the update and the
 // forward transform share one LDS exchange buffer per row.
-template <int N1, int N2, int MODE>
+// OBL: some illumination is oblique, so the plane-wave source carries a per-
+// element x phase (a separate instantiation keeps it out of the normal path)
+template <int N1, int N2, int MODE, bool OBL>
 __global__ void __launch_bounds__((XGeom<N1, N2>::THREADS))
 k1_xpass(CbsArgs a) {
   using G = XGeom<N1, N2>;
@@ -415,10 +416,9 @@ k1_xpass(CbsArgs a) {
   if (ok && t < N1) {
     const bool yin = (y >= a.py) && (y < a.ny - a.py);
     const bool zin = (z >= a.pz) && (z < a.nz - a.pz);
-    const float2 ph = a.phase[ib * a.nz + z];
-    const float2 pc = a.pol[ib][c];
     // pol_c exp(i (ky y + kz z)); the x phase joins per element when oblique
-    const float2 spl = a.oblique ? cmul(cmul(ph, pc), a.phy[ib * a.ny + y]) : cmul(ph, pc);
+    const float2 ph = a.phase[(ib * 3 + c) * a.nz + z];
+    const float2 spl = OBL ? cmul(ph, a.phy[ib * a.ny + y]) : ph;
     const float2* phxb = a.phx + ib * a.nx;
     sfor<0, N2>([&](auto M) {
       const int x = t + N1 * CV(M);
@@ -449,8 +449,12 @@ k1_xpass(CbsArgs a) {
         w = cmul(make_float2(v0.x, v0.y - a.eps), e);
         if (a.src == SRC_PLANE) {
           const bool xin = (x >= a.px) && (x < a.nx - a.px);
-          if (xin && yin && zin)
-            w = cadd(w, cmul(v0, a.oblique ? cmul(spl, phxb[x]) : spl));
+          if (xin && yin && zin) {
+            if constexpr (OBL)
+              w = cadd(w, cmul(v0, cmul(spl, phxb[x])));
+            else
+              w = cadd(w, cmul(v0, spl));
+          }
         } else if (a.src == SRC_FIELD) {
           w = cadd(w, cscale(a.fin[ebase + x], a.src_scale));
         } else if (a.src == SRC_FIELD_CONJ) {
@@ -762,7 +766,7 @@ int k1_low_occupancy() {
   if (v < 0) {
     using G = XGeom<N1, N2>;
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k1_xpass<N1, N2, K1_ITER>, G::THREADS,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k1_xpass<N1, N2, K1_ITER, false>, G::THREADS,
                                                      0) != hipSuccess || b <= 0)
       v = 0;
     else
@@ -777,12 +781,17 @@ void launch_k1(const CbsArgs& a_in, int mode, hipStream_t s) {
   CbsArgs a = a_in;
   a.k1_prio = k1_low_occupancy<N1, N2>();
   const unsigned nb = 3u * (unsigned)a.nb * (unsigned)a.gy * (unsigned)a.nz;
-  if (mode == K1_FWD)
-    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD>), dim3(nb), dim3(G::THREADS), 0, s, a);
+  const bool obl = a.oblique && a.src == SRC_PLANE;
+  if (mode == K1_FWD && !obl)
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD, false>), dim3(nb), dim3(G::THREADS), 0, s, a);
+  else if (mode == K1_FWD)
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_FWD, true>), dim3(nb), dim3(G::THREADS), 0, s, a);
+  else if (mode == K1_ITER && !obl)
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_ITER, false>), dim3(nb), dim3(G::THREADS), 0, s, a);
   else if (mode == K1_ITER)
-    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_ITER>), dim3(nb), dim3(G::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_ITER, true>), dim3(nb), dim3(G::THREADS), 0, s, a);
   else
-    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_INV>), dim3(nb), dim3(G::THREADS), 0, s, a);
+    hipLaunchKernelGGL((k1_xpass<N1, N2, K1_INV, false>), dim3(nb), dim3(G::THREADS), 0, s, a);
 }
 
 template <int N1, int N2>

@@ -2,9 +2,10 @@
 
 * Three illuminations of one medium -- x- and y-polarised at normal incidence
   and a p-polarised wave at oblique incidence -- in one batch: at equal
-  iteration counts every field is bit-identical to the single solve of its
-  source, and each matches the FP64 oracle's plane wave of that polarisation
-  and direction (equal iterations 1e-4, converged 1e-3).
+  iteration counts each field equals the single solve of its source (bit for
+  bit where both run the same x-pass instantiation), and each matches the
+  FP64 oracle's plane wave of that polarisation and direction (equal
+  iterations 1e-4, converged 1e-3).
 * The batch stops when its largest residual reaches tol; every illumination's
   own residual is reported.
 """
@@ -57,11 +58,28 @@ def test_batch_equals_single_solves_and_oracle(device):
     assert all(s.iterations == k and s.status == L.CBS_NOT_CONVERGED for s in sts)
     for b, (pol, d) in enumerate(ILLUM):
         E1, s1 = p.solve(tol=0.0, max_iter=k, pol=pol, direction=d)
-        assert torch.equal(Eb[b], E1), b
-        assert s1.residual == sts[b].residual
+        if d == (0.0, 0.0):
+            # a normal-incidence wave inside a batch that holds an oblique one runs
+            # the x pass compiled with the per-element x phase (exactly 1 here):
+            # the same arithmetic up to the compiler's FMA contraction
+            assert rel(Eb[b].cpu().numpy(), E1.cpu().numpy()) < 1e-6, b
+        else:
+            assert torch.equal(Eb[b], E1), b
+            assert s1.residual == sts[b].residual
         Eo, res = oc.solve_forward(g, eps, tol=0.0, max_iter=k, pol=pol, direction=d)
         assert rel(E1.cpu().numpy(), Eo) < 1e-4, b
         assert abs(sts[b].residual - res.eta) < 1e-4 * res.eta
+    p.close()
+
+
+def test_normal_incidence_batch_is_bit_identical_to_single_solves(device):
+    g, p, eps = setup(device, seed=122)
+    illum = ILLUM[:2]
+    Eb, sts = p.solve_batch(illum, tol=0.0, max_iter=20, check_every=6)
+    for b, (pol, d) in enumerate(illum):
+        E1, s1 = p.solve(tol=0.0, max_iter=20, pol=pol, direction=d)
+        assert torch.equal(Eb[b], E1), b
+        assert s1.residual == sts[b].residual
     p.close()
 
 
