@@ -144,3 +144,105 @@ def reflection_normal(n: int, pitch: float, lambda0: float, pml: int, alpha_max:
     z = np.arange(n) * pitch
     a, b, res = _ab.fit_counterpropagating(e[lo:hi], z[lo:hi], k)
     return abs(b / a) ** 2, res
+
+
+# ---------------------------------------------------------------------------
+# The stretched operator applied with FFTs, and its solve by GMRES on the CBS
+# preconditioned system (grids too large for dense LU)
+# ---------------------------------------------------------------------------
+def _deriv_axis(f: np.ndarray, axis: int, symbol: np.ndarray) -> np.ndarray:
+    """F^-1 diag(symbol) F along one numpy axis of f."""
+    shape = [1] * f.ndim
+    shape[axis] = symbol.size
+    return np.fft.ifft(symbol.reshape(shape) * np.fft.fft(f, axis=axis), axis=axis)
+
+
+def stretched_apply(g: "_cbs.Grid", E: np.ndarray, alpha_max: float, order: int = 2) -> np.ndarray:
+    """L_s E for a field [3, nz, ny, nx], term by term as in the module notes:
+
+        (L_s E)_c = - sum_{b != c} S_b^-1 D_b S_b^-1 D_b E_c
+                    + sum_{b != c} S_c^-1 T_c S_b^-1 T_b E_b  +  N_c E_c
+
+    with every 1D operator applied by FFT along its axis (the same operator
+    as ``operator_dense``, which forms it as a matrix)."""
+    E = np.asarray(E, dtype=np.complex128)
+    dims = (g.nx, g.ny, g.nz)
+    np_axis = (3, 2, 1)   # numpy axis of x, y, z in a [3, nz, ny, nx] array
+    D, T, N, Si = [], [], [], []
+    for a in range(3):
+        p, pt = _dense._freq_1d(dims[a], g.pitch)
+        D.append(1j * p)
+        T.append(1j * pt)
+        N.append(p * p - pt * pt)
+        shape = [1, 1, 1, 1]
+        shape[np_axis[a]] = dims[a]
+        Si.append((1.0 / stretch_1d(dims[a], g.pml[a], alpha_max, order)).reshape(shape))
+
+    def dS(f, a, sym):   # S_a^-1 (derivative with symbol sym along a) f
+        return Si[a] * _deriv_axis(f, np_axis[a], sym[a])
+
+    out = np.zeros_like(E)
+    for c in range(3):
+        Ec = E[c:c + 1]
+        acc = _deriv_axis(Ec, np_axis[c], N[c].astype(np.complex128))
+        for b in range(3):
+            if b == c:
+                continue
+            acc = acc - dS(dS(Ec, b, D), b, D)
+            acc = acc + dS(dS(E[b:b + 1], b, T), c, T)
+        out[c] = acc[0]
+    return out
+
+
+def delta_apply(g: "_cbs.Grid", E: np.ndarray, alpha_max: float, order: int = 2) -> np.ndarray:
+    """(L_s - L) E: what the stretched layer adds to the solver's operator."""
+    return stretched_apply(g, E, alpha_max, order) - _cbs.curl_curl_apply(g, E)
+
+
+def gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, alpha_max: float,
+                order: int = 2, rtol: float = 1e-10, restart: int = 20, maxiter: int = 200,
+                callback=None, require_convergence: bool = True):
+    """E_s = A_s^-1 S by FP64 GMRES, A_s = L_s - k0^2 eps_r (no absorbing
+    potential: the grid must have sigma_max = 0).
+
+    The CBS splitting (references [25], [26]) with G = (L - kb^2 - i eps)^-1,
+    V = k0^2 eps_r - kb^2 - i eps and gamma = 1 + i V0/eps turns A_s E = S into
+
+        gamma [E - G (V E - (L_s - L) E)] = gamma G S
+
+    (multiply A_s = (L - kb^2 - i eps) - V + (L_s - L) by gamma G).  The CBS
+    step with the source S - (L_s - L) E is E + (right side - left side), so
+    this is the CBS iteration's own preconditioned system with the stretched
+    derivatives added; GMRES solves it where the fixed-point iteration cannot
+    (G (L_s - L) is not a contraction).  Restarted GMRES(restart) from E = 0;
+    maxiter counts restart cycles; rtol is the relative residual of this
+    system.  Returns (E_s [3, nz, ny, nx], relative residual)."""
+    import scipy.sparse.linalg as spla
+    if g.sigma_max != 0.0:
+        raise ValueError("the stretched layer replaces the graded potential: sigma_max must be 0")
+    pot = _cbs.potentials(g, eps_r)
+    shp = (3,) + g.vshape
+    N3 = 3 * g.n_vox
+    gam = pot.gamma[None]
+    V = pot.V[None]
+
+    def mv(v):
+        E = np.asarray(v).reshape(shp)
+        W = V * E - delta_apply(g, E, alpha_max, order)
+        return (gam * (E - _cbs.green_apply(g, W, pot.kt2))).reshape(-1)
+
+    M = spla.LinearOperator((N3, N3), matvec=mv, dtype=np.complex128)
+    b = (gam * _cbs.green_apply(g, np.asarray(S, dtype=np.complex128), pot.kt2)).reshape(-1)
+    steps = [0]
+
+    def cb(r):
+        steps[0] += 1
+        if callback is not None:
+            callback(steps[0], float(r))
+
+    x, info = spla.gmres(M, b, rtol=rtol, atol=0.0, restart=restart, maxiter=maxiter,
+                         callback=cb, callback_type="pr_norm")
+    res = float(np.linalg.norm(b - mv(x)) / np.linalg.norm(b))
+    if info != 0 and require_convergence:
+        raise RuntimeError(f"GMRES did not converge (info={info}, residual {res:.3e})")
+    return x.reshape(shp), res
