@@ -232,6 +232,60 @@ int cbs_solve_batch(cbs_plan_t plan, int count, const cbs_source* srcs, void* E_
  * for plans whose solve has stopped.  Every plan must have a solve begun. */
 int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out);
 
+/* ---- stretched-coordinate absorbing layer -------------------------------
+ * The paper's absorbing layer is a "perfectly matching" one after reference
+ * [31] (simulation-setup paragraph), a stretched-coordinate PML.  Here every
+ * derivative d/da inside the layer of axis a becomes (1/s_a) d/da with
+ * s_a = 1 + i alpha_max u_a^order (u_a the depth into the layer in units of its
+ * thickness, outermost voxel u = 1, the same u as the graded potential's), on the
+ * solver's spectral derivatives.  The system (L_s - k0^2 eps_r) E_s = S is not a
+ * CBS splitting (the stretched derivatives are not a bounded potential), so it is
+ * solved by restarted GMRES on the CBS-preconditioned form
+ *     gamma [E_s - G (V E_s - (L_s - L) E_s)] = gamma G S
+ * whose operator is one CBS iteration with the field source -(L_s - L) E_s plus
+ * the per-axis stretched-derivative products.  The plan must have no graded
+ * potential (cbs_plan_set_pml_profile(plan, order, 0) before
+ * cbs_set_permittivity): the stretched layer replaces it. */
+typedef struct {
+  double alpha_max;   /* >= 0; 0 turns the layer off (then the solve is the plain
+                         spectral problem on the periodic grid)                   */
+  int order;          /* 1..8, the profile exponent                              */
+  int restart;        /* GMRES restart length, 1..64 (workspace grows with it)   */
+} cbs_scpml;
+
+/* Device bytes of the stretched-layer workspace: restart + 1 basis fields, the
+ * right-hand side, the stretched-derivative source, two scalar fields, the dense
+ * per-axis operators (4 n_a^2 complex64 per axis) and reduction buffers.  0 if
+ * the grid is not supported, an axis exceeds 1024 or restart is out of range. */
+size_t cbs_scpml_workspace_bytes(int nx, int ny, int nz, int restart);
+
+/* Solve with the stretched layer.
+ *   src        as cbs_solve (plane wave, field, point or none)
+ *   E_dev      complex64 [3][nz][ny][nx]: E_inc + E_s for a plane wave (E_s with
+ *              CBS_RETURN_SCATTERED), E_s otherwise; overwritten from zero
+ *   opts       tol: relative residual ||b - B E_s|| / ||b|| of the preconditioned
+ *              system (FP64 norms, the true residual at the end of a restart
+ *              cycle); max_iter: GMRES steps (one operator application each);
+ *              flags: CBS_RETURN_SCATTERED, CBS_RECORD_HISTORY (cbs_history then
+ *              gives the GMRES residual estimate of every step); CBS_WARM_START
+ *              is rejected; check_every is ignored
+ *   layer      alpha_max, order, restart
+ *   stats      iterations = GMRES steps, residual = the last true residual
+ *   work_dev   >= cbs_scpml_workspace_bytes(nx, ny, nz, layer->restart), 256-byte
+ *              aligned, owned by the caller
+ * Returns CBS_OK, CBS_NOT_CONVERGED (E_dev holds the last iterate), CBS_E_STATE
+ * for a plan with a graded potential, or an error.  Synchronises the plan's
+ * stream after every step (the host runs the Givens rotations). */
+int cbs_solve_scpml(cbs_plan_t plan, const cbs_source* src, void* E_dev, const cbs_opts* opts,
+                    const cbs_scpml* layer, cbs_stats* stats, void* work_dev, size_t work_bytes);
+
+/* The stretched layer's addition to the operator, out = (L_s - L) in (units
+ * 1/m^2), for complex64 [3][nz][ny][nx] fields in != out.  work_dev as for
+ * cbs_solve_scpml with restart = 1 (layer->restart is ignored).  Asynchronous on
+ * the plan's stream. */
+int cbs_scpml_operator(cbs_plan_t plan, const cbs_scpml* layer, const void* in_dev,
+                       void* out_dev, void* work_dev, size_t work_bytes);
+
 /* Permittivity gradient over a half-open box [lo, hi) (x, y, z):
  *   grad[z][y][x] = scale * k0^2 * Re(sum_c E_adj,c * E_c)
  * (dK/d eps_r = k0^2; scale = 2 for the adjoint source conj(E(r0)) of

@@ -10,6 +10,8 @@
 #include <cstring>
 #include <algorithm>
 #include <chrono>
+#include <climits>
+#include <complex>
 #include <mutex>
 #include <new>
 #include <string>
@@ -17,6 +19,7 @@
 
 #include "../../include/cbs.h"
 #include "kernels.hpp"
+#include "scpml.hpp"
 
 namespace cbs {
 
@@ -504,9 +507,7 @@ __global__ void k_tfsf_inverse(TfsfArgs t) {
   }
 }
 
-__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
+// zmul: complex FP64 product (scpml.hpp)
 __device__ __forceinline__ double2 zmul3(double2 a, double2 b, double2 c) {
   return zmul(zmul(a, b), c);
 }
@@ -1776,6 +1777,393 @@ int cbs_bandwidth_probe(const void* src, void* dst, size_t bytes, int reps, void
   (void)hipEventDestroy(e1);
   if (rc == CBS_OK) *ms_out = ms / reps;
   return rc;
+}
+
+// ---------------------------------------------------------------------------
+// stretched-coordinate layer (reference [31]): per-axis operators, the
+// operator of the preconditioned system and its GMRES solve
+// ---------------------------------------------------------------------------
+namespace {
+
+struct ScpmlLayout {
+  size_t basis, b, F, X, Y, mats[3], cols[3], part, h, y, total;
+};
+
+bool scpml_layout(int nx, int ny, int nz, int restart, ScpmlLayout& S) {
+  if (restart < 1 || restart > kScpmlMaxRestart) return false;
+  const int dims[3] = {nx, ny, nz};
+  for (int a = 0; a < 3; ++a)
+    if (dims[a] < 2 || dims[a] > kScpmlMaxAxis) return false;
+  const size_t N = (size_t)nx * ny * nz;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  S.basis = take((size_t)(restart + 1) * 3 * N * sizeof(float2));
+  S.b = take(3 * N * sizeof(float2));
+  S.F = take(3 * N * sizeof(float2));
+  S.X = take(N * sizeof(float2));
+  S.Y = take(N * sizeof(float2));
+  for (int a = 0; a < 3; ++a) S.mats[a] = take(4 * (size_t)dims[a] * dims[a] * sizeof(float2));
+  for (int a = 0; a < 3; ++a) S.cols[a] = take(5 * (size_t)dims[a] * sizeof(double2));
+  S.part = take((size_t)(kScpmlMaxRestart + 1) * kGmBlocks * sizeof(double2));
+  S.h = take((size_t)3 * (kScpmlMaxRestart + 1) * sizeof(double2));
+  S.y = take((size_t)(kScpmlMaxRestart + 1) * sizeof(double2));
+  S.total = off;
+  return true;
+}
+
+struct Scpml {
+  cbs_plan_s* p;
+  int dims[3];
+  long long N, n3;            // voxels; complex values of a vector field
+  float2 *basis, *b, *F, *X, *Y;
+  const float2 *A[3], *B[3], *C[3], *T[3];
+  double2 *part, *h, *y;
+  float2* vec(int i) const { return basis + (long long)i * n3; }
+};
+
+int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, size_t bytes,
+                Scpml& s) {
+  if (!layer) return fail(CBS_E_INVALID, "layer parameters are NULL");
+  if (!(layer->alpha_max >= 0.0) || !std::isfinite(layer->alpha_max))
+    return fail(CBS_E_INVALID, "alpha_max must be finite and >= 0");
+  if (layer->order < 1 || layer->order > 8) return fail(CBS_E_INVALID, "order must be in [1, 8]");
+  ScpmlLayout S;
+  if (!scpml_layout(p->nx, p->ny, p->nz, restart, S))
+    return fail(CBS_E_INVALID, "restart must be in [1, %d] and every axis <= %d", kScpmlMaxRestart,
+                kScpmlMaxAxis);
+  if (!work) return fail(CBS_E_WORKSPACE, "stretched-layer workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(work) % 256 != 0)
+    return fail(CBS_E_WORKSPACE, "stretched-layer workspace must be 256-byte aligned");
+  if (bytes < S.total)
+    return fail(CBS_E_WORKSPACE, "stretched-layer workspace %zu bytes < required %zu", bytes, S.total);
+  char* base = static_cast<char*>(work);
+  s.p = p;
+  s.dims[0] = p->nx;
+  s.dims[1] = p->ny;
+  s.dims[2] = p->nz;
+  s.N = (long long)p->nx * p->ny * p->nz;
+  s.n3 = 3 * s.N;
+  s.basis = reinterpret_cast<float2*>(base + S.basis);
+  s.b = reinterpret_cast<float2*>(base + S.b);
+  s.F = reinterpret_cast<float2*>(base + S.F);
+  s.X = reinterpret_cast<float2*>(base + S.X);
+  s.Y = reinterpret_cast<float2*>(base + S.Y);
+  s.part = reinterpret_cast<double2*>(base + S.part);
+  s.h = reinterpret_cast<double2*>(base + S.h);
+  s.y = reinterpret_cast<double2*>(base + S.y);
+  for (int a = 0; a < 3; ++a) {
+    const int n = s.dims[a];
+    float2* m = reinterpret_cast<float2*>(base + S.mats[a]);
+    double2* col = reinterpret_cast<double2*>(base + S.cols[a]);
+    s.A[a] = m;
+    s.B[a] = m + (size_t)n * n;
+    s.C[a] = m + 2 * (size_t)n * n;
+    s.T[a] = m + 3 * (size_t)n * n;
+    hipLaunchKernelGGL(k_scpml_columns, dim3((n + 127) / 128), dim3(128), 0, p->stream, n,
+                       p->pml[a], layer->order, layer->alpha_max, col, col + n, col + 2 * n,
+                       col + 3 * n, col + 4 * n);
+    HIP_LAUNCHED();
+    const long long nn = (long long)n * n;
+    hipLaunchKernelGGL(k_scpml_matrices, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
+                       p->stream, n, p->pml[a], col, col + n, col + 2 * n, col + 3 * n,
+                       col + 4 * n, const_cast<float2*>(s.A[a]), const_cast<float2*>(s.B[a]),
+                       const_cast<float2*>(s.C[a]), const_cast<float2*>(s.T[a]));
+    HIP_LAUNCHED();
+  }
+  return CBS_OK;
+}
+
+// out = alpha M in (+ out) along axis `axis` of scalar [nz][ny][nx] fields
+int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in, float2* out,
+                    float alpha, bool accumulate) {
+  AxisMM a;
+  a.M = M;
+  a.in = in;
+  a.out = out;
+  a.n = s.dims[axis];
+  a.Q = axis == 0 ? 1 : (axis == 1 ? s.dims[0] : s.dims[0] * s.dims[1]);
+  a.L = s.N / a.n;
+  a.alpha = alpha;
+  a.accumulate = accumulate ? 1 : 0;
+  const dim3 grid((unsigned)((a.L + kMmTL - 1) / kMmTL), (unsigned)((a.n + kMmTI - 1) / kMmTI));
+  hipLaunchKernelGGL(k_axis_mm, grid, dim3(256), 0, s.p->stream, a);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// F = alpha (L_s - L) v:  per component c, sum_{b != c} A_b v_c + B_c v_c +
+// C_c X - T_c Y with X = sum_b C_b v_b, Y = sum_b T_b v_b (an axis without a
+// layer has A = B = 0 exactly and is skipped)
+int enqueue_delta(const Scpml& s, const float2* v, float2* F, float alpha) {
+  const long long N = s.N;
+  const int* pml = s.p->pml;
+  int rc;
+  for (int b = 0; b < 3; ++b) {
+    if ((rc = enqueue_axis_mm(s, b, s.C[b], v + b * N, s.X, 1.0f, b > 0))) return rc;
+    if ((rc = enqueue_axis_mm(s, b, s.T[b], v + b * N, s.Y, 1.0f, b > 0))) return rc;
+  }
+  for (int c = 0; c < 3; ++c) {
+    float2* Fc = F + c * N;
+    const float2* vc = v + c * N;
+    if ((rc = enqueue_axis_mm(s, c, s.C[c], s.X, Fc, alpha, false))) return rc;
+    if ((rc = enqueue_axis_mm(s, c, s.T[c], s.Y, Fc, -alpha, true))) return rc;
+    if (pml[c] > 0 && (rc = enqueue_axis_mm(s, c, s.B[c], vc, Fc, alpha, true))) return rc;
+    for (int b = 0; b < 3; ++b)
+      if (b != c && pml[b] > 0 && (rc = enqueue_axis_mm(s, b, s.A[b], vc, Fc, alpha, true)))
+        return rc;
+  }
+  return CBS_OK;
+}
+
+void gm_grid(long long n, dim3& g) {
+  g = dim3((unsigned)std::min<long long>((n + kGmThreads - 1) / kGmThreads, 8192));
+}
+
+// w = B v = v - (the CBS step from v with the field source -(L_s - L) v):
+// B = gamma [I - G (V - (L_s - L))], the CBS-preconditioned stretched operator
+int enqueue_operator(const Scpml& s, const float2* v, float2* w) {
+  cbs_plan_s* p = s.p;
+  int rc = enqueue_delta(s, v, s.F, -1.0f);
+  if (rc) return rc;
+  dim3 g;
+  gm_grid(s.n3, g);
+  hipLaunchKernelGGL(k_gm_copy, g, dim3(kGmThreads), 0, p->stream, v, w, s.n3);
+  HIP_LAUNCHED();
+  CbsArgs a = base_args(p);
+  a.E = w;
+  a.src = SRC_FIELD;
+  a.fin = s.F;
+  a.src_scale = 1.0f;   // F is already in units of the pitch
+  a.warm = 1;
+  p->ox->k1(a, K1_FWD, p->stream);
+  if ((rc = enqueue_iteration(p, a))) return rc;
+  hipLaunchKernelGGL(k_gm_rsub, g, dim3(kGmThreads), 0, p->stream, v, w, s.n3);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// h[0..cnt) = V[0..cnt)^H w (vectors of n3 values, V_i = V + i n3)
+int enqueue_dots(const Scpml& s, const float2* V, int cnt, const float2* w, double2* h) {
+  hipLaunchKernelGGL(k_gm_dots, dim3(kGmBlocks, cnt), dim3(kGmThreads), 0, s.p->stream, V, s.n3,
+                     w, s.n3, s.part);
+  HIP_LAUNCHED();
+  hipLaunchKernelGGL(k_gm_dots_finish, dim3(cnt), dim3(kGmThreads), 0, s.p->stream, s.part,
+                     kGmBlocks, h);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// w += sign sum_i c_i V_i
+int enqueue_update(const Scpml& s, int cnt, const double2* c, float sign, float2* w) {
+  dim3 g;
+  gm_grid(s.n3, g);
+  hipLaunchKernelGGL(k_gm_update, g, dim3(kGmThreads), 0, s.p->stream, s.basis, s.n3, cnt, c,
+                     sign, w, s.n3);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+int enqueue_scale(const Scpml& s, float2* w, double f) {
+  dim3 g;
+  gm_grid(s.n3, g);
+  hipLaunchKernelGGL(k_gm_scale, g, dim3(kGmThreads), 0, s.p->stream, w, s.n3, (float)f);
+  HIP_LAUNCHED();
+  return CBS_OK;
+}
+
+// copy n device double2 to the host and wait for the stream
+int read_back(cbs_plan_s* p, const double2* dev, std::complex<double>* host, int n) {
+  HIP_TRY(hipMemcpyAsync(host, dev, n * sizeof(double2), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return CBS_OK;
+}
+
+// Restarted GMRES(m) on B x = b from x = 0 (x in E_dev).  Arnoldi with
+// classical Gram-Schmidt applied twice (two fused dot/update passes), Givens
+// rotations on the host in FP64; at the end of each cycle the true residual
+// b - B x gives the restart vector and the reported residual.
+int scpml_gmres(const Scpml& s, float2* x, int m, const cbs_opts* o, double beta0, int* iters,
+                double* rel_out, std::vector<double>& hist) {
+  cbs_plan_s* p = s.p;
+  using cd = std::complex<double>;
+  std::vector<cd> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(3 * (m + 1)), y(m + 1);
+  auto Hij = [&](int i, int j) -> cd& { return H[(size_t)j * (m + 1) + i]; };
+  int total = 0, rc;
+  double beta = beta0, rel = 1.0;
+  // V_0 = b / beta0
+  dim3 gg;
+  gm_grid(s.n3, gg);
+  hipLaunchKernelGGL(k_gm_copy, gg, dim3(kGmThreads), 0, p->stream, s.b, s.vec(0), s.n3);
+  HIP_LAUNCHED();
+  if ((rc = enqueue_scale(s, s.vec(0), 1.0 / beta0))) return rc;
+  while (true) {
+    std::fill(g.begin(), g.end(), cd(0));
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m && total < o->max_iter; ++j) {
+      float2* w = s.vec(j + 1);
+      if ((rc = enqueue_operator(s, s.vec(j), w))) return rc;
+      double2* h0 = s.h;
+      double2* h1 = s.h + (m + 1);
+      double2* h2 = s.h + 2 * (m + 1);
+      if ((rc = enqueue_dots(s, s.basis, j + 1, w, h0))) return rc;
+      if ((rc = enqueue_update(s, j + 1, h0, -1.0f, w))) return rc;
+      if ((rc = enqueue_dots(s, s.basis, j + 1, w, h1))) return rc;
+      if ((rc = enqueue_update(s, j + 1, h1, -1.0f, w))) return rc;
+      if ((rc = enqueue_dots(s, w, 1, w, h2))) return rc;
+      if ((rc = read_back(p, s.h, hv.data(), 3 * (m + 1)))) return rc;
+      const double hn = std::sqrt(std::max(0.0, hv[2 * (m + 1)].real()));
+      for (int i = 0; i <= j; ++i) Hij(i, j) = hv[i] + hv[(m + 1) + i];
+      Hij(j + 1, j) = hn;
+      for (int i = 0; i <= j; ++i)
+        if (!std::isfinite(Hij(i, j).real()) || !std::isfinite(Hij(i, j).imag()))
+          return fail(CBS_E_DIVERGED, "non-finite Arnoldi coefficient after %d steps", total);
+      if (!std::isfinite(hn)) return fail(CBS_E_DIVERGED, "non-finite norm after %d steps", total);
+      if (hn > 0.0 && (rc = enqueue_scale(s, w, 1.0 / hn))) return rc;
+      // previous rotations, then the one that zeroes H(j+1, j)
+      for (int i = 0; i < j; ++i) {
+        const cd t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+        Hij(i + 1, j) = -std::conj(sn[i]) * Hij(i, j) + cs[i] * Hij(i + 1, j);
+        Hij(i, j) = t;
+      }
+      const cd a = Hij(j, j);
+      const double r = std::hypot(std::abs(a), hn);
+      cs[j] = r > 0 ? cd(std::abs(a) / r) : cd(1.0);
+      sn[j] = r > 0 ? (std::abs(a) > 0 ? (a / std::abs(a)) * hn / r : cd(1.0)) : cd(0.0);
+      Hij(j, j) = cs[j] * a + sn[j] * hn;
+      Hij(j + 1, j) = 0.0;
+      g[j + 1] = -std::conj(sn[j]) * g[j];
+      g[j] = cs[j] * g[j];
+      ++total;
+      ++k;
+      const double est = std::abs(g[j + 1]) / beta0;
+      hist.push_back(est);
+      if (est <= o->tol || hn <= 1e-300) break;
+    }
+    // x += V y, H(0..k, 0..k) y = g
+    for (int i = k - 1; i >= 0; --i) {
+      cd t = g[i];
+      for (int l = i + 1; l < k; ++l) t -= Hij(i, l) * y[l];
+      y[i] = t / Hij(i, i);
+    }
+    if (k > 0) {
+      HIP_TRY(hipMemcpyAsync(s.y, y.data(), k * sizeof(double2), hipMemcpyHostToDevice, p->stream));
+      if ((rc = enqueue_update(s, k, s.y, 1.0f, x))) return rc;
+    }
+    // true residual r = b - B x into V_0
+    if ((rc = enqueue_operator(s, x, s.vec(0)))) return rc;
+    hipLaunchKernelGGL(k_gm_rsub, gg, dim3(kGmThreads), 0, p->stream, s.b, s.vec(0), s.n3);
+    HIP_LAUNCHED();
+    if ((rc = enqueue_dots(s, s.vec(0), 1, s.vec(0), s.h))) return rc;
+    if ((rc = read_back(p, s.h, hv.data(), 1))) return rc;   // also retires the y upload
+    beta = std::sqrt(std::max(0.0, hv[0].real()));
+    if (!std::isfinite(beta)) return fail(CBS_E_DIVERGED, "non-finite residual after %d steps", total);
+    rel = beta / beta0;
+    if (rel <= o->tol || total >= o->max_iter || k == 0) break;
+    if ((rc = enqueue_scale(s, s.vec(0), 1.0 / beta))) return rc;
+  }
+  *iters = total;
+  *rel_out = rel;
+  return CBS_OK;
+}
+
+}  // namespace
+
+size_t cbs_scpml_workspace_bytes(int nx, int ny, int nz, int restart) {
+  ScpmlLayout S;
+  if (!find_size(nx) || !find_size(ny) || !find_size(nz)) return 0;
+  return scpml_layout(nx, ny, nz, restart, S) ? S.total : 0;
+}
+
+int cbs_scpml_operator(cbs_plan_t p, const cbs_scpml* layer, const void* in, void* out,
+                       void* work, size_t work_bytes) {
+  int rc = check_plan(p, false);
+  if (rc) return rc;
+  if (!in || !out) return fail(CBS_E_INVALID, "NULL field");
+  if (in == out) return fail(CBS_E_INVALID, "in and out must not alias");
+  if (p->act.on) return fail(CBS_E_STATE, "a solve is in progress on this plan");
+  Scpml s;
+  if ((rc = scpml_setup(p, layer, 1, work, work_bytes, s))) return rc;
+  // the operators are in units of the pitch: 1/d^2 gives 1/m^2
+  return enqueue_delta(s, static_cast<const float2*>(in), static_cast<float2*>(out),
+                       (float)(1.0 / (p->pitch * p->pitch)));
+}
+
+int cbs_solve_scpml(cbs_plan_t p, const cbs_source* src, void* E_dev, const cbs_opts* o,
+                    const cbs_scpml* layer, cbs_stats* stats, void* work, size_t work_bytes) {
+  int rc = check_plan(p, true);
+  if (rc) return rc;
+  if ((rc = check_opts(o))) return rc;
+  if (!E_dev) return fail(CBS_E_INVALID, "output field is NULL");
+  if (p->act.on) return fail(CBS_E_STATE, "a solve is in progress on this plan");
+  if (p->sigma_max != 0.0)
+    return fail(CBS_E_STATE, "the stretched layer replaces the graded potential: set the "
+                             "plan's sigma_max to 0 (cbs_plan_set_pml_profile) first");
+  if (o->flags & CBS_WARM_START)
+    return fail(CBS_E_INVALID, "the stretched-layer solve starts from zero (no CBS_WARM_START)");
+  if (!layer) return fail(CBS_E_INVALID, "layer parameters are NULL");
+  Scpml s;
+  if ((rc = scpml_setup(p, layer, layer->restart, work, work_bytes, s))) return rc;
+  const auto t0 = std::chrono::steady_clock::now();
+  // b = gamma G S: one CBS step from zero with the solve's source
+  CbsArgs a = base_args(p);
+  Kvec kv;
+  if ((rc = set_source(p, a, src, false, kv))) return rc;
+  cbs_opts so = *o;
+  so.flags = 0;
+  so.tol = -1.0;            // the step count never stops the passes
+  so.max_iter = INT_MAX;
+  if ((rc = enqueue_solve_start(p, a, &so, src, nullptr, kv))) return rc;
+  a.E = s.b;
+  a.warm = 0;
+  p->ox->k1(a, K1_FWD, p->stream);
+  if ((rc = enqueue_iteration(p, a))) return rc;
+  float2* x = static_cast<float2*>(E_dev);
+  dim3 gg;
+  gm_grid(s.n3, gg);
+  hipLaunchKernelGGL(k_gm_copy, gg, dim3(kGmThreads), 0, p->stream, nullptr, x, s.n3);
+  HIP_LAUNCHED();
+  std::complex<double> bb;
+  if ((rc = enqueue_dots(s, s.b, 1, s.b, s.h))) return rc;
+  if ((rc = read_back(p, s.h, &bb, 1))) return rc;
+  const double beta0 = std::sqrt(std::max(0.0, bb.real()));
+  if (!std::isfinite(beta0)) return fail(CBS_E_DIVERGED, "non-finite source");
+  std::vector<double> hist;
+  int iters = 0;
+  double rel = 0.0;
+  if (beta0 > 0.0 && (rc = scpml_gmres(s, x, layer->restart, o, beta0, &iters, &rel, hist)))
+    return rc;
+  if (a.src == SRC_PLANE && !(o->flags & CBS_RETURN_SCATTERED)) {
+    CbsArgs ai = a;
+    ai.E = x;
+    hipLaunchKernelGGL(k_incident, dim3(2048), dim3(256), 0, p->stream, ai, 1.0f);
+    HIP_LAUNCHED();
+  }
+  DevState ds;
+  HIP_TRY(hipMemcpyAsync(&ds, p->state, sizeof(DevState), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  if (ds.status == 3) return fail(CBS_E_DIVERGED, "non-finite field in a CBS step");
+  p->hist_len = 0;
+  if ((o->flags & CBS_RECORD_HISTORY) && !hist.empty()) {
+    const int n = std::min<int>((int)hist.size(), kHistCap);
+    HIP_TRY(hipMemcpy(p->hist, hist.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    p->hist_len = n;
+  }
+  const bool ok = rel <= o->tol;
+  if (stats) {
+    stats->iterations = iters;
+    stats->converged = ok ? 1 : 0;
+    stats->residual = rel;
+    stats->eps_shift = p->eps;
+    stats->ms = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (ok) return CBS_OK;
+  g_err = "max_iter reached before the residual met tol";
+  return CBS_NOT_CONVERGED;
 }
 
 int cbs_history(cbs_plan_t p, double* out, int max) {

@@ -1,0 +1,305 @@
+// Stretched-coordinate absorbing layer (reference [31] of arXiv 2506.15411,
+// named in its simulation-setup paragraph) for the spectral vector operator,
+// and the vector kernels of the GMRES solve that uses it.
+//
+// In a stretched layer every derivative d/da becomes (1/s_a) d/da with
+// s_a = 1 + i alpha_max u_a^m (u_a the depth into the layer of axis a, the
+// graded potential's u).  With the solver's spectral derivatives D_a (symbol
+// i p), T_a (symbol i pt, pt = p except 0 at the Nyquist bin of an even axis)
+// and S_a = diag(s_a), the stretched operator differs from L = F^-1 (|p|^2 I -
+// pt pt^T) F by
+//
+//   ((L_s - L) E)_c = sum_{b != c} A_b E_c + B_c E_c + C_c X - T_c Y,
+//   X = sum_b C_b E_b,   Y = sum_b T_b E_b,
+//   A_a = D_a^2 - S_a^-1 D_a S_a^-1 D_a,  B_a = T_a^2 - S_a^-1 T_a S_a^-1 T_a,
+//   C_a = S_a^-1 T_a,
+//
+// every term a 1D operator along one axis.  Each is stored as a dense n x n
+// matrix (built in FP64 on the device from the circulant columns of D, T, D^2,
+// T^2) and applied to all lines of a field by a tiled complex GEMM.  Work is
+// in units of the pitch (p d in [-pi, pi]).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cbs {
+
+constexpr int kScpmlMaxRestart = 64;   // GMRES basis <= 65 vectors
+constexpr int kScpmlMaxAxis = 1024;
+constexpr int kGmBlocks = 512;         // fixed grid of the FP64 dot products
+constexpr int kGmThreads = 256;
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ double2 zsub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+
+// depth u in (0, 1] into a layer of p voxels on each side of an axis of n
+// voxels (outermost voxel 1, first layer voxel next to the interior 1/p), else 0
+__device__ __forceinline__ double stretch_depth(int i, int n, int p) {
+  if (p <= 0) return 0.0;
+  if (i < p) return double(p - i) / double(p);
+  if (i >= n - p) return double(i - (n - p - 1)) / double(p);
+  return 0.0;
+}
+
+// Circulant columns (pitch 1) of D (i p), T (i pt), D^2 (-p^2), T^2 (-pt^2)
+// along one axis: col[m] = (1/n) sum_k sym_k exp(2 pi i k m / n), p_k = 2 pi
+// f_k / n with f_k the FFT-order frequency (the Nyquist bin of an even axis
+// negative); and 1/s over the axis.  One thread per m, FP64.
+__global__ void k_scpml_columns(int n, int pml, int order, double alpha, double2* d,
+                                double2* t, double2* dd, double2* tt, double2* sinv) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double dx = 0, dy = 0, tx = 0, ty = 0, ddx = 0, ddy = 0, ttx = 0, tty = 0;
+  for (int k = 0; k < n; ++k) {
+    const int f = 2 * k < n ? k : k - n;
+    const double p = 2.0 * M_PI * f / n;
+    const double pt = (2 * k == n) ? 0.0 : p;
+    const long long km = ((long long)k * m) % n;
+    double s, c;
+    sincospi(2.0 * (double)km / n, &s, &c);
+    // (i q) (c + i s) = -q s + i q c
+    dx -= p * s;
+    dy += p * c;
+    tx -= pt * s;
+    ty += pt * c;
+    ddx -= p * p * c;
+    ddy -= p * p * s;
+    ttx -= pt * pt * c;
+    tty -= pt * pt * s;
+  }
+  const double inv = 1.0 / n;
+  d[m] = make_double2(dx * inv, dy * inv);
+  t[m] = make_double2(tx * inv, ty * inv);
+  dd[m] = make_double2(ddx * inv, ddy * inv);
+  tt[m] = make_double2(ttx * inv, tty * inv);
+  double u = stretch_depth(m, n, pml), um = 1.0;
+  for (int k = 0; k < order; ++k) um *= u;
+  const double a = alpha * um;   // s = 1 + i a, 1/s = (1 - i a) / (1 + a^2)
+  sinv[m] = make_double2(1.0 / (1.0 + a * a), -a / (1.0 + a * a));
+}
+
+// The four n x n operators of one axis, row-major FP32:
+//   A = D^2 - S^-1 D S^-1 D,  B = T^2 - S^-1 T S^-1 T,  C = S^-1 T,  T.
+// (S^-1 D S^-1 D)_ij = s_i^-1 (D^2_ij + sum_{k in layer} D_ik (s_k^-1 - 1) D_kj):
+// only layer voxels have s_k != 1.  One thread per entry, FP64.
+__global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2* t,
+                                 const double2* dd, const double2* tt, const double2* sinv,
+                                 float2* A, float2* B, float2* C, float2* T) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (long long)n * n) return;
+  const int i = (int)(e / n), j = (int)(e % n);
+  const int ij = ((i - j) % n + n) % n;
+  double2 sd = make_double2(0, 0), st = make_double2(0, 0);
+  auto layer_term = [&](int k) {
+    const double2 w = make_double2(sinv[k].x - 1.0, sinv[k].y);
+    const int ik = ((i - k) % n + n) % n, kj = ((k - j) % n + n) % n;
+    sd = zadd(sd, zmul(zmul(d[ik], w), d[kj]));
+    st = zadd(st, zmul(zmul(t[ik], w), t[kj]));
+  };
+  const int p = pml < 0 ? 0 : pml;
+  for (int k = 0; k < p; ++k) layer_term(k);
+  for (int k = n - p; k < n; ++k)
+    if (k >= p) layer_term(k);
+  const double2 si = sinv[i];
+  const double2 a = zsub(dd[ij], zmul(si, zadd(dd[ij], sd)));
+  const double2 b = zsub(tt[ij], zmul(si, zadd(tt[ij], st)));
+  const double2 c = zmul(si, t[ij]);
+  A[e] = make_float2((float)a.x, (float)a.y);
+  B[e] = make_float2((float)b.x, (float)b.y);
+  C[e] = make_float2((float)c.x, (float)c.y);
+  T[e] = make_float2((float)t[ij].x, (float)t[ij].y);
+}
+
+// out(l, i) = alpha sum_j M[i][j] in(l, j)  (+ out(l, i) if accumulate) for every
+// line l of a scalar [nz][ny][nx] field along one axis of length n: element i of
+// line l sits at (l / Q) n Q + l % Q + i Q (Q = 1 along x, nx along y, nx ny
+// along z).  Tiles of 64 lines x 64 outputs, j staged through LDS 16 at a time;
+// each thread accumulates 4 x 4 complex products.
+struct AxisMM {
+  const float2* M;
+  const float2* in;
+  float2* out;
+  int n, Q;
+  long long L;      // lines
+  float alpha;
+  int accumulate;
+};
+
+constexpr int kMmTL = 64, kMmTI = 64, kMmTJ = 16;
+
+__device__ __forceinline__ long long axis_addr(long long l, int i, int n, int Q) {
+  return (l / Q) * (long long)n * Q + l % Q + (long long)i * Q;
+}
+
+__global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
+  __shared__ float2 sIn[kMmTJ][kMmTL + 1];
+  __shared__ float2 sM[kMmTJ][kMmTI + 1];
+  const int tid = threadIdx.x;
+  const long long l0 = (long long)blockIdx.x * kMmTL;
+  const int i0 = blockIdx.y * kMmTI;
+  // along x (Q = 1) consecutive lanes take consecutive outputs i, otherwise
+  // consecutive lines (both are contiguous in memory)
+  const bool rowwise = a.Q == 1;
+  const int tl = rowwise ? tid / 16 : tid % 16;
+  const int ti = rowwise ? tid % 16 : tid / 16;
+  float2 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc[r][s] = make_float2(0.f, 0.f);
+
+  for (int j0 = 0; j0 < a.n; j0 += kMmTJ) {
+#pragma unroll
+    for (int e = 0; e < (kMmTL * kMmTJ) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      const int jj = rowwise ? idx % kMmTJ : idx / kMmTL;
+      const int ll = rowwise ? idx / kMmTJ : idx % kMmTL;
+      const long long l = l0 + ll;
+      const int j = j0 + jj;
+      sIn[jj][ll] = (l < a.L && j < a.n) ? a.in[axis_addr(l, j, a.n, a.Q)] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < (kMmTI * kMmTJ) / 256; ++e) {
+      const int idx = tid + 256 * e;
+      const int jj = idx % kMmTJ, ii = idx / kMmTJ;
+      const int i = i0 + ii, j = j0 + jj;
+      sM[jj][ii] = (i < a.n && j < a.n) ? a.M[(long long)i * a.n + j] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int jj = 0; jj < kMmTJ; ++jj) {
+      float2 b[4], m[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) b[r] = sIn[jj][tl + 16 * r];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) m[s] = sM[jj][ti + 16 * s];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc[r][s].x = fmaf(m[s].x, b[r].x, fmaf(-m[s].y, b[r].y, acc[r][s].x));
+          acc[r][s].y = fmaf(m[s].x, b[r].y, fmaf(m[s].y, b[r].x, acc[r][s].y));
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const long long l = l0 + tl + 16 * r;
+      const int i = i0 + ti + 16 * s;
+      if (l < a.L && i < a.n) {
+        const long long o = axis_addr(l, i, a.n, a.Q);
+        float2 v = make_float2(a.alpha * acc[r][s].x, a.alpha * acc[r][s].y);
+        if (a.accumulate) {
+          const float2 w = a.out[o];
+          v.x += w.x;
+          v.y += w.y;
+        }
+        a.out[o] = v;
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// GMRES vector kernels: fields of n complex FP32 values, reductions in FP64
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 block_sum_z(double sx, double sy, double2* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    sx += __shfl_down(sx, o);
+    sy += __shfl_down(sy, o);
+  }
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (lane == 0) red[wv] = make_double2(sx, sy);
+  __syncthreads();
+  double2 r = make_double2(0, 0);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)blockDim.x / 64; ++k) r = zadd(r, red[k]);
+  return r;   // valid in thread 0
+}
+
+// part[i][blk] = partial of sum_e conj(V_i[e]) w[e], i = blockIdx.y; fixed grid,
+// fixed order, so the result does not depend on timing
+__global__ void __launch_bounds__(kGmThreads)
+k_gm_dots(const float2* V, long long vstride, const float2* w, long long n, double2* part) {
+  __shared__ double2 red[kGmThreads / 64];
+  const float2* v = V + blockIdx.y * vstride;
+  double sx = 0, sy = 0;
+  for (long long e = (long long)blockIdx.x * kGmThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kGmThreads) {
+    const float2 a = v[e], b = w[e];
+    sx += (double)a.x * b.x + (double)a.y * b.y;
+    sy += (double)a.x * b.y - (double)a.y * b.x;
+  }
+  const double2 r = block_sum_z(sx, sy, red);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = r;
+}
+
+// h[i] = sum over blocks of part[i][.], one work-group per i
+__global__ void __launch_bounds__(kGmThreads)
+k_gm_dots_finish(const double2* part, int nblk, double2* h) {
+  __shared__ double2 red[kGmThreads / 64];
+  const double2* p = part + blockIdx.x * nblk;
+  double sx = 0, sy = 0;
+  for (int k = threadIdx.x; k < nblk; k += kGmThreads) {
+    sx += p[k].x;
+    sy += p[k].y;
+  }
+  const double2 r = block_sum_z(sx, sy, red);
+  if (threadIdx.x == 0) h[blockIdx.x] = r;
+}
+
+// w += sign sum_{i < cnt} c_i V_i, coefficients c (FP64) in device memory
+__global__ void __launch_bounds__(kGmThreads)
+k_gm_update(const float2* V, long long vstride, int cnt, const double2* c, float sign,
+            float2* w, long long n) {
+  __shared__ float2 cf[kScpmlMaxRestart + 1];
+  if (threadIdx.x < cnt)
+    cf[threadIdx.x] = make_float2((float)(sign * c[threadIdx.x].x), (float)(sign * c[threadIdx.x].y));
+  __syncthreads();
+  for (long long e = (long long)blockIdx.x * kGmThreads + threadIdx.x; e < n;
+       e += (long long)gridDim.x * kGmThreads) {
+    float2 acc = w[e];
+    for (int i = 0; i < cnt; ++i) {
+      const float2 v = V[i * vstride + e];
+      acc.x = fmaf(cf[i].x, v.x, fmaf(-cf[i].y, v.y, acc.x));
+      acc.y = fmaf(cf[i].x, v.y, fmaf(cf[i].y, v.x, acc.y));
+    }
+    w[e] = acc;
+  }
+}
+
+// w = s w
+__global__ void k_gm_scale(float2* w, long long n, float s) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float2 v = w[e];
+    w[e] = make_float2(s * v.x, s * v.y);
+  }
+}
+
+// w = a - w
+__global__ void k_gm_rsub(const float2* a, float2* w, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float2 x = a[e], v = w[e];
+    w[e] = make_float2(x.x - v.x, x.y - v.y);
+  }
+}
+
+// dst = src (or 0 when src is null)
+__global__ void k_gm_copy(const float2* src, float2* dst, long long n) {
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = src ? src[e] : make_float2(0.f, 0.f);
+}
+
+}  // namespace cbs

@@ -60,6 +60,11 @@ class cbs_source(ctypes.Structure):
                 ("amp", (ctypes.c_double * 2) * 3), ("dir", ctypes.c_double * 2)]
 
 
+class cbs_scpml(ctypes.Structure):
+    _fields_ = [("alpha_max", ctypes.c_double), ("order", ctypes.c_int),
+                ("restart", ctypes.c_int)]
+
+
 class CbsError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"cbs status {code}: {msg}")
@@ -74,7 +79,7 @@ SYMBOLS = [
     "cbs_solve_begin", "cbs_solve_advance", "cbs_solve_poll", "cbs_solve_end", "cbs_batch_step",
     "cbs_gradient", "cbs_lens_metrics", "cbs_apply_green", "cbs_time_passes", "cbs_bandwidth_probe", "cbs_history", "cbs_eps_shift", "cbs_plan_destroy",
     "cbs_last_error", "cbs_solve_static", "cbs_batch_workspace_bytes", "cbs_solve_batch",
-    "cbs_tfsf_source",
+    "cbs_tfsf_source", "cbs_scpml_workspace_bytes", "cbs_solve_scpml", "cbs_scpml_operator",
 ]
 
 CBS_MAX_ILLUMINATIONS = 8
@@ -151,6 +156,14 @@ def load(path: str | None = None):
     lib.cbs_solve_batch.restype = c_int
     lib.cbs_tfsf_source.argtypes = [c_void_p, P(cbs_source), P(c_int), P(c_int), c_void_p]
     lib.cbs_tfsf_source.restype = c_int
+    lib.cbs_scpml_workspace_bytes.argtypes = [c_int, c_int, c_int, c_int]
+    lib.cbs_scpml_workspace_bytes.restype = c_size_t
+    lib.cbs_solve_scpml.argtypes = [c_void_p, P(cbs_source), c_void_p, P(cbs_opts), P(cbs_scpml),
+                                    P(cbs_stats), c_void_p, c_size_t]
+    lib.cbs_solve_scpml.restype = c_int
+    lib.cbs_scpml_operator.argtypes = [c_void_p, P(cbs_scpml), c_void_p, c_void_p, c_void_p,
+                                       c_size_t]
+    lib.cbs_scpml_operator.restype = c_int
     lib.cbs_last_error.argtypes = []
     lib.cbs_last_error.restype = ctypes.c_char_p
     if path is None:
@@ -325,6 +338,26 @@ def cbs_solve_batch(plan, srcs, E_ptr, opts: cbs_opts, work_ptr, work_bytes):
 def cbs_tfsf_source(plan, src: cbs_source | None, lo, hi, S_ptr):
     return check(load().cbs_tfsf_source(plan, ctypes.byref(src) if src is not None else None,
                                         _ints3(lo), _ints3(hi), ctypes.c_void_p(S_ptr)))
+
+
+def cbs_scpml_workspace_bytes(nx, ny, nz, restart) -> int:
+    return int(load().cbs_scpml_workspace_bytes(nx, ny, nz, restart))
+
+
+def cbs_solve_scpml(plan, src: cbs_source | None, E_ptr, opts: cbs_opts, layer: cbs_scpml,
+                    work_ptr, work_bytes):
+    st = cbs_stats()
+    code = load().cbs_solve_scpml(plan, ctypes.byref(src) if src is not None else None,
+                                  ctypes.c_void_p(E_ptr), ctypes.byref(opts), ctypes.byref(layer),
+                                  ctypes.byref(st), ctypes.c_void_p(work_ptr), work_bytes)
+    check(code, allow_not_converged=True)
+    return code, st
+
+
+def cbs_scpml_operator(plan, layer: cbs_scpml, in_ptr, out_ptr, work_ptr, work_bytes):
+    return check(load().cbs_scpml_operator(plan, ctypes.byref(layer), ctypes.c_void_p(in_ptr),
+                                           ctypes.c_void_p(out_ptr), ctypes.c_void_p(work_ptr),
+                                           work_bytes))
 
 
 def cbs_last_error() -> str:

@@ -205,6 +205,46 @@ class Plan:
                                     raw.data_ptr() + off, nbytes)
         return E, [_stats(rc, st) for st in sts]
 
+    def _scpml_work(self, restart):
+        nbytes = L.cbs_scpml_workspace_bytes(*self.shape, int(restart))
+        if nbytes == 0:
+            raise ValueError(f"restart {restart}: 1..64 supported, every axis <= 1024")
+        with torch.cuda.stream(self.stream):
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        return raw, raw.data_ptr() + (-raw.data_ptr()) % 256, nbytes
+
+    def solve_scpml(self, E: torch.Tensor | None = None, alpha_max=1.5, order=2, restart=40,
+                    tol=1e-5, max_iter=2000, scattered=False, history=False, pol=None,
+                    field=None, point=None, kind=None, direction=None):
+        """Forward solve with the stretched-coordinate layer instead of the graded
+        potential (see cbs_solve_scpml; the plan must have sigma_max = 0).  tol is
+        the relative residual of the preconditioned system, max_iter counts GMRES
+        steps.  Returns (E, SolveStats)."""
+        if E is None:
+            E = self.new_field()
+        _require_gpu(E, "E", torch.complex64, self.fshape)
+        src = self._forward_source(pol, field, point, kind, direction)
+        raw, ptr, nbytes = self._scpml_work(restart)
+        layer = L.cbs_scpml(float(alpha_max), int(order), int(restart))
+        rc, st = L.cbs_solve_scpml(self.handle, src, E.data_ptr(),
+                                   self._opts(tol, max_iter, 1, False, scattered, history),
+                                   layer, ptr, nbytes)
+        del raw   # the call synchronised the plan's stream
+        return E, _stats(rc, st)
+
+    def scpml_operator(self, v: torch.Tensor, alpha_max=1.5, order=2,
+                       out: torch.Tensor | None = None) -> torch.Tensor:
+        """(L_s - L) v in 1/m^2 (see cbs_scpml_operator)."""
+        _require_gpu(v, "v", torch.complex64, self.fshape)
+        if out is None:
+            out = self.new_field()
+        _require_gpu(out, "out", torch.complex64, self.fshape)
+        raw, ptr, nbytes = self._scpml_work(1)
+        L.cbs_scpml_operator(self.handle, L.cbs_scpml(float(alpha_max), int(order), 1),
+                             v.data_ptr(), out.data_ptr(), ptr, nbytes)
+        self.stream.synchronize()   # the workspace is released on return
+        return out
+
     # -- asynchronous solves (one at a time per plan; plans overlap) ---------
     def begin(self, E: torch.Tensor, adjoint=False, E_fwd=None, r0=None, amp=None, field=None,
               tol=1e-4, max_iter=20000, warm=False, scattered=False, history=False, pol=None):
