@@ -159,7 +159,8 @@ def serving(dev, n_requests: int, loads, tol: float):
         "tol": tol, "max_iter_per_solve": SERVE_MAX_ITER,
         "scheduler": {"max_active": srv.max_active, "inflight_quanta": srv.inflight,
                       "quantum_target_ms": srv.target_ms,
-                      "exclusive_after_s": srv.exclusive_after_s},
+                      "exclusive_after_s": srv.exclusive_after_s,
+                      "exclusive_quantum_scale": srv.exclusive_scale},
         "mean_service_s": round(mean_service, 4),
         "one_at_a_time_method": "FIFO recurrence over the measured back-to-back service times",
         "iterations_per_grid": {k: {"median": int(np.median(v)), "max": int(max(v))}
@@ -360,6 +361,10 @@ def main(argv=None):
                          "CBS iterations of the workload (one launch of each pass per "
                          "iteration) and a 1 GiB device copy used to calibrate memory "
                          "counters; prints no JSON line")
+    ap.add_argument("--scpml-steps", type=int, default=0,
+                    help="measurement mode: this many GMRES steps of the stretched-layer "
+                         "solve (alpha_max 1.5, order 2, restart 40, no graded potential) "
+                         "on the workload's scene; logs ms per step, prints no JSON line")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -389,6 +394,19 @@ def main(argv=None):
     log(f"[bench] building scene {args.workload}")
     sc = workload(args.workload)
     eps = torch.from_numpy(sc.eps_r).to(dev)
+    if args.scpml_steps > 0:
+        sp = Plan(sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml, device=dev, sigma_max=0.0)
+        sp.set_permittivity(eps)
+        Es = sp.new_field()
+        sp.solve_scpml(Es, restart=40, tol=0.0, max_iter=2)   # tables, first launches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = sp.solve_scpml(Es, restart=40, tol=0.0, max_iter=args.scpml_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        log(f"[bench] stretched layer on {sc.name}: {st.iterations} GMRES steps, "
+            f"{1e3 * dt / st.iterations:.2f} ms per step, residual {st.residual:.3e}")
+        return 0
     plan = Plan(sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml, device=dev)
     plan_order, plan_sigma, plan_kappa = 2, 1.0, 1.1     # the Plan defaults
     E = plan.new_field()

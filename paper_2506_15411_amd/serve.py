@@ -20,8 +20,8 @@ Active solves advance in quanta of about 4 ms of device work, each on its own
 stream.  A request whose solve has run for longer than `exclusive_after_s`
 since admission is given the device alone: no new request is admitted and the
 other active solves get no further quanta until it completes (their queued
-quanta drain), and it advances in quanta four times longer with one more in
-flight.  One large solve saturates HBM by itself, so sharing the device
+quanta drain), and it advances in quanta `exclusive_scale` times longer with one
+more in flight.  One large solve saturates HBM by itself, so sharing the device
 with it only stretches it; short requests keep overlapping freely.  This keeps
 the latency of the few long solves near their one-at-a-time service time while
 the many short ones are served concurrently.
@@ -129,7 +129,8 @@ class Server:
 
     def __init__(self, device=None, max_active: int = 4, budget_bytes: int | None = None,
                  tol: float = 1e-4, max_iter: int = 20000, inflight: int = 2,
-                 target_ms: float = 4.0, exclusive_after_s: float | None = 0.25):
+                 target_ms: float = 4.0, exclusive_after_s: float | None = 0.05,
+                 exclusive_scale: int = 2):
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.device)
@@ -141,6 +142,7 @@ class Server:
         self.inflight = inflight
         self.target_ms = target_ms
         self.exclusive_after_s = exclusive_after_s
+        self.exclusive_scale = int(exclusive_scale)
         self.idle = collections.defaultdict(list)   # key -> [_Slot]
         self.used = 0
         self.refused = 0
@@ -291,7 +293,7 @@ class Server:
                 elif job is excl and outstanding < self.inflight + 1:
                     # alone on the device: longer quanta, one more in flight, so
                     # the host's polling never leaves it idle
-                    job.slot.plan.advance(4 * job.quantum)
+                    job.slot.plan.advance(self.exclusive_scale * job.quantum)
                     progressed = True
                 elif excl is None and outstanding < self.inflight:
                     job.slot.plan.advance(job.quantum)
