@@ -129,8 +129,8 @@ class Server:
 
     def __init__(self, device=None, max_active: int = 4, budget_bytes: int | None = None,
                  tol: float = 1e-4, max_iter: int = 20000, inflight: int = 2,
-                 target_ms: float = 4.0, exclusive_after_s: float | None = 0.05,
-                 exclusive_scale: int = 2):
+                 target_ms: float = 4.0, exclusive_after_s: float | None = 0.25,
+                 exclusive_scale: int = 4):
         self.device = torch.device(device) if device is not None else torch.device("cuda", 0)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(self.device)

@@ -35,7 +35,10 @@ sphere64_fd  The 64^3 sphere at lambda/6 with a 6-voxel seeded design slab: the
 Long solves run in chunks of 50 iterations (each chunk continues exactly where
 the previous stopped: the iteration depends only on the current field) and
 write a checkpoint to the directory named by --ckpt, so an interrupted run
-resumes.
+resumes.  --tol (default 1e-6) is the eta at which the lens solves stop; a
+fixture stores the eta it reached and the error estimate above, and the GPU
+tests compare against it within the larger of 1e-3 and three times that
+estimate.
 """
 
 from __future__ import annotations
@@ -92,19 +95,19 @@ def converge(g, eps, S, tag, ckpt_dir, tol=TOL, max_iter=20000):
     return E, done, h, rho, err
 
 
-def lens16(ckpt):
+def lens16(ckpt, tol=TOL):
     sc = scenes.zoneplate16()
     g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
     oc.validate(g, sc.eps_r)
     E, its, hist, rho, err = converge(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r),
-                                      "lens16_fwd", ckpt)
+                                      "lens16_fwd", ckpt, tol)
     nx, ny, nz = sc.shape
     x0, y0, z0 = sc.r0
     rng = np.random.default_rng(7)
     vz, vy, vx = rng.integers(0, nz, 4096), rng.integers(0, ny, 4096), rng.integers(0, nx, 4096)
     out = os.path.join(HERE, "lens16_converged.npz")
     np.savez_compressed(
-        out, shape=np.array(sc.shape), r0=np.array(sc.r0), tol=TOL, iterations=its,
+        out, shape=np.array(sc.shape), r0=np.array(sc.r0), tol=tol, iterations=its,
         eta=hist[-1], contraction=rho, error_estimate=err,
         eps_shift=oc.potentials(g, sc.eps_r).eps,
         focal_plane=E[:, z0].astype(np.complex64),          # [3, ny, nx] at z = z0
@@ -114,12 +117,12 @@ def lens16(ckpt):
     log(f"wrote {out}: {its} iterations, eta {hist[-1]:.3e}")
 
 
-def lens16_grad(ckpt):
+def lens16_grad(ckpt, tol=TOL):
     sc = scenes.zoneplate16_design(0)
     g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
     oc.validate(g, sc.eps_r)
     Es, it1, h1, rho1, err1 = converge(g, sc.eps_r, oc.plane_wave_source(g, sc.eps_r),
-                                       "lens16d_fwd", ckpt)
+                                       "lens16d_fwd", ckpt, tol)
     E = oc.plane_wave(g) + Es
     del Es
     # the adjoint source conj(E(r0)) delta_{r0} is a sum of three unit dipoles at
@@ -130,7 +133,7 @@ def lens16_grad(ckpt):
     Ea = np.zeros_like(E)
     it2, rho2, err2, eta2 = 0, 0.0, 0.0, 0.0
     for c in range(3):
-        Gc, itc, hc, rhoc, errc = dipole(g, sc, c, ckpt)
+        Gc, itc, hc, rhoc, errc = dipole(g, sc, c, ckpt, tol)
         Ea += w[c] * Gc
         del Gc
         it2, rho2, err2, eta2 = max(it2, itc), max(rho2, rhoc), max(err2, errc), max(eta2, hc[-1])
@@ -143,7 +146,7 @@ def lens16_grad(ckpt):
     out = os.path.join(HERE, "lens16_gradient_converged.npz")
     np.savez_compressed(
         out, shape=np.array(sc.shape), r0=np.array(sc.r0), box_lo=np.array(lo),
-        box_hi=np.array(hi), tol=TOL, iterations=np.array([it1, it2]),
+        box_hi=np.array(hi), tol=tol, iterations=np.array([it1, it2]),
         eta=np.array([h1[-1], h2[-1]]), contraction=np.array([rho1, rho2]),
         error_estimate=np.array([err1, err2]), objective=oc.focal_objective(E, sc.r0),
         vox=np.stack([vx, vy, vz]), vox_grad=grad[vz, vy, vx],
@@ -151,17 +154,17 @@ def lens16_grad(ckpt):
     log(f"wrote {out}")
 
 
-def dipole(g, sc, c, ckpt):
+def dipole(g, sc, c, ckpt, tol=TOL):
     """A^-1 (delta_{r0} e_c): the unit dipole at the focus, component c."""
     amp = [0.0, 0.0, 0.0]
     amp[c] = 1.0
-    return converge(g, sc.eps_r, oc.point_source(g, sc.r0, amp), f"lens16d_dip{c}", ckpt)
+    return converge(g, sc.eps_r, oc.point_source(g, sc.r0, amp), f"lens16d_dip{c}", ckpt, tol)
 
 
-def lens16_dipole(ckpt, c):
+def lens16_dipole(ckpt, c, tol=TOL):
     sc = scenes.zoneplate16_design(0)
     g = oc.Grid(*sc.shape, sc.pitch, sc.lambda0, sc.n_bg, sc.pml)
-    dipole(g, sc, c, ckpt)
+    dipole(g, sc, c, ckpt, tol)
 
 
 def sphere64_slab():
@@ -216,14 +219,17 @@ def main(argv=None):
                     choices=["lens16", "lens16_grad", "sphere64_fd", "lens16_dipole0",
                              "lens16_dipole1", "lens16_dipole2"])
     ap.add_argument("--ckpt", default=None, help="directory for resumable checkpoints")
+    ap.add_argument("--tol", type=float, default=TOL, help="eta at which the lens solves stop")
     a = ap.parse_args(argv)
     if a.ckpt:
         os.makedirs(a.ckpt, exist_ok=True)
     for w in a.which:
         if w.startswith("lens16_dipole"):
-            lens16_dipole(a.ckpt, int(w[-1]))
+            lens16_dipole(a.ckpt, int(w[-1]), a.tol)
+        elif w == "sphere64_fd":
+            sphere64_fd(a.ckpt)
         else:
-            {"lens16": lens16, "lens16_grad": lens16_grad, "sphere64_fd": sphere64_fd}[w](a.ckpt)
+            {"lens16": lens16, "lens16_grad": lens16_grad}[w](a.ckpt, a.tol)
 
 
 if __name__ == "__main__":

@@ -2,11 +2,12 @@
 (oracle only; see that script for how each was computed).
 
 * 275 x 275 x 315 zone plate (the Fig. 1 benchmark lens): the GPU's scattered
-  field at tol 1e-6 against the oracle's at eta <= 1e-9 on the focal plane, the
-  xz plane through the axis, 4096 seeded voxels and the whole-volume norm.
+  field at tol 1e-6 against the FP64 CBS field the fixture stores (its own eta
+  and estimated error are stored with it) on the focal plane, the xz plane
+  through the axis, 4096 seeded voxels and the whole-volume norm.
 * The same lens with its seeded design slab: forward and adjoint to tol 1e-6,
-  the gradient of |E(r0)|^2 over the slab against the oracle's converged
-  adjoint gradient (4096 slab voxels, the slab's middle plane, the norm).
+  the gradient of |E(r0)|^2 over the slab against the oracle's adjoint gradient
+  (4096 slab voxels, the slab's middle plane, the norm).
 * 64^3 sphere with a 6-voxel design slab: the GPU adjoint gradient against FP64
   central differences at 32 voxels (each within 1e-3 of the difference).
 * The same slab gradient checked by a random +-1 directional difference on the
@@ -14,7 +15,9 @@
 
 Tolerance at convergence: 1e-3 relative (the FP32 iteration stops at eta 1e-6;
 its distance to the exact solution is about eta / (1 - rho) plus FP32
-round-off).
+round-off), or three times the fixture's own estimated error where that is
+larger (the FP64 iteration of these lenses contracts by only about 0.999 per
+step at the end, so its solution carries an error of about 1000 eta).
 """
 
 import os
@@ -44,6 +47,15 @@ def rel(a, b):
                  / np.linalg.norm(np.asarray(b).ravel()))
 
 
+def fixture_tol(gd):
+    """1e-3, or three times the fixture's estimated relative error if larger"""
+    est = float(np.max(np.atleast_1d(gd["error_estimate"])))
+    tol = max(1e-3, 3.0 * est)
+    print(f"fixture eta {np.atleast_1d(gd['eta']).tolist()}, estimated error {est:.1e}: "
+          f"tolerance {tol:.1e}")
+    return tol
+
+
 def check_samples(got, want, what, tol=1e-3):
     """relative L2 over the samples, and every sample within tol of the
     samples' rms magnitude"""
@@ -67,13 +79,14 @@ def test_lens16_converged_field_vs_fp64_fixture(device):
     assert st.status == L.CBS_OK
     print(f"GPU {st.iterations} iterations to {st.residual:.2e}; FP64 solution's own "
           f"eta {float(gd['eta']):.2e}")
+    tol = fixture_tol(gd)
     x0, y0, z0 = sc.r0
-    check_samples(E[:, z0].cpu().numpy(), gd["focal_plane"], "focal plane")
-    check_samples(E[:, :, y0, :].cpu().numpy(), gd["xz_plane"], "xz plane")
+    check_samples(E[:, z0].cpu().numpy(), gd["focal_plane"], "focal plane", tol)
+    check_samples(E[:, :, y0, :].cpu().numpy(), gd["xz_plane"], "xz plane", tol)
     vx, vy, vz = (torch.from_numpy(v).to(device) for v in gd["vox"])
-    check_samples(E[:, vz, vy, vx].cpu().numpy(), gd["vox_E"], "4096 voxels")
+    check_samples(E[:, vz, vy, vx].cpu().numpy(), gd["vox_E"], "4096 voxels", tol)
     norm = float(torch.linalg.vector_norm(E.to(torch.complex128)).item())
-    assert abs(norm - float(gd["norm"])) < 1e-3 * float(gd["norm"])
+    assert abs(norm - float(gd["norm"])) < tol * float(gd["norm"])
     # how far a solve to the configs' tol 1e-4 is from the converged field
     E4, s4 = p.solve(tol=1e-4, max_iter=20000, scattered=True)
     d4 = rel(E4[:, vz, vy, vx].cpu().numpy(), gd["vox_E"])
@@ -95,16 +108,18 @@ def test_lens16_converged_gradient_vs_fp64_fixture(device):
     assert s1.status == L.CBS_OK and s2.status == L.CBS_OK
     print(f"GPU {s1.iterations} + {s2.iterations} iterations; FP64 solutions' own eta "
           f"{list(gd['eta'])}")
+    tol = fixture_tol(gd)
     x0, y0, z0 = sc.r0
     fom = float((E[:, z0, y0, x0].abs() ** 2).sum().item())
-    assert fom == pytest.approx(float(gd["objective"]), rel=1e-3)
+    assert fom == pytest.approx(float(gd["objective"]), rel=tol)
     grad = p.gradient(E, Ea, lo, hi, scale=2.0)
     vx, vy, vz = (torch.from_numpy(v).to(device) for v in gd["vox"])
-    check_samples(grad[vz, vy, vx].double().cpu().numpy(), gd["vox_grad"], "4096 slab voxels")
+    check_samples(grad[vz, vy, vx].double().cpu().numpy(), gd["vox_grad"], "4096 slab voxels",
+                  tol)
     bz = grad.shape[0]
-    check_samples(grad[bz // 2].double().cpu().numpy(), gd["mid_plane"], "slab middle plane")
+    check_samples(grad[bz // 2].double().cpu().numpy(), gd["mid_plane"], "slab middle plane", tol)
     norm = float(torch.linalg.vector_norm(grad.double()).item())
-    assert abs(norm - float(gd["norm"])) < 1e-3 * float(gd["norm"])
+    assert abs(norm - float(gd["norm"])) < tol * float(gd["norm"])
     p.close()
 
 
