@@ -363,7 +363,7 @@ def main(argv=None):
                          "counters; prints no JSON line")
     ap.add_argument("--scpml-steps", type=int, default=0,
                     help="measurement mode: this many GMRES steps of the stretched-layer "
-                         "solve (alpha_max 1.5, order 2, restart 40, no graded potential) "
+                         "solve (alpha_max 0.75, order 1, restart 40, no graded potential) "
                          "on the workload's scene; logs ms per step, prints no JSON line")
     args = ap.parse_args(argv)
 

@@ -11,8 +11,9 @@ simulation-setup paragraph) on the GPU, against the FP64 oracle.
   24 x 20 x 32 (tests/golden/make_scpml.py).
 * Reflection at normal incidence on the z layers of the 621 x 621 x 261 volume
   (18 voxels of 177 nm) and of the 64^3 sphere case (8 voxels at lambda/6, the
-  thickness of its lateral layers): below the graded potential's by orders of
-  magnitude, near the oracle's exact 1D value.
+  thickness of its lateral layers), for alpha_max 1.5 (quadratic) and the
+  default 0.75 (linear): below the graded potential's by orders of magnitude,
+  near the oracle's exact 1D value.
 """
 
 import os
@@ -118,8 +119,9 @@ def test_converged_matches_fp64_fixture(device):
     p.close()
 
 
+@pytest.mark.parametrize("alpha,order", [(1.5, 2), (0.75, 1)])
 @pytest.mark.parametrize("case", ["621x621x261 z layer", "64^3 lateral thickness"])
-def test_reflection_below_graded_potential(case, device):
+def test_reflection_below_graded_potential(case, alpha, order, device):
     nz, pitch, pz = {"621x621x261 z layer": (261, 177e-9, 18),
                      "64^3 lateral thickness": (64, LAM / 6, 8)}[case]
     shape, pml = (4, 4, nz), (0, 0, pz)
@@ -128,13 +130,14 @@ def test_reflection_below_graded_potential(case, device):
     S = ab.oblique_source(g, 0, "s", z_src, amp=g.k0 ** 2)
     Sd = torch.from_numpy(S.astype(np.complex64)).to(device)
     p = plan(shape, pml, device, pitch=pitch)
-    E, st = p.solve_scpml(alpha_max=1.5, restart=40, tol=2e-7, max_iter=4000, field=Sd)
+    E, st = p.solve_scpml(alpha_max=alpha, order=order, restart=40, tol=2e-7, max_iter=4000,
+                          field=Sd)
     assert st.status == L.CBS_OK
     R_s, _ = ab.reflection_from_field(g, E.cpu().numpy().astype(np.complex128), 0, "s", z_src)
-    R_1d, _ = scpml.reflection_normal(nz, pitch, LAM, pz, 1.5, 2)
+    R_1d, _ = scpml.reflection_normal(nz, pitch, LAM, pz, alpha, order)
     R_graded, _ = ab.reflection_normal(nz, pitch, LAM, pz)
-    print(f"{case}: R stretched gpu {R_s:.2e} (oracle 1D {R_1d:.2e}, {st.iterations} steps), "
-          f"graded potential {R_graded:.2e}")
+    print(f"{case}, alpha {alpha} order {order}: R stretched gpu {R_s:.2e} (oracle 1D "
+          f"{R_1d:.2e}, {st.iterations} steps), graded potential {R_graded:.2e}")
     assert R_s < R_graded / 100
     # at R ~ 1e-11 the FP32 field resolves the returning wave to about 1e-1 of itself
     assert abs(R_s - R_1d) <= 0.3 * R_1d + 1e-12
