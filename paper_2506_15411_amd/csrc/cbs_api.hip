@@ -1786,7 +1786,7 @@ int cbs_bandwidth_probe(const void* src, void* dst, size_t bytes, int reps, void
 namespace {
 
 struct ScpmlLayout {
-  size_t basis, b, F, X, Y, mats[3], cols[3], part, h, y, total;
+  size_t basis, b, F, X, Z, mats[3], cols[3], part, h, y, total;
 };
 
 bool scpml_layout(int nx, int ny, int nz, int restart, ScpmlLayout& S) {
@@ -1805,8 +1805,9 @@ bool scpml_layout(int nx, int ny, int nz, int restart, ScpmlLayout& S) {
   S.b = take(3 * N * sizeof(float2));
   S.F = take(3 * N * sizeof(float2));
   S.X = take(N * sizeof(float2));
-  S.Y = take(N * sizeof(float2));
-  for (int a = 0; a < 3; ++a) S.mats[a] = take(4 * (size_t)dims[a] * dims[a] * sizeof(float2));
+  S.Z = take(N * sizeof(float2));
+  for (int a = 0; a < 3; ++a)
+    S.mats[a] = take((4 * (size_t)dims[a] * dims[a] + dims[a]) * sizeof(float2));
   for (int a = 0; a < 3; ++a) S.cols[a] = take(5 * (size_t)dims[a] * sizeof(double2));
   S.part = take((size_t)(kScpmlMaxRestart + 1) * kGmBlocks * sizeof(double2));
   S.h = take((size_t)3 * (kScpmlMaxRestart + 1) * sizeof(double2));
@@ -1819,8 +1820,8 @@ struct Scpml {
   cbs_plan_s* p;
   int dims[3];
   long long N, n3;            // voxels; complex values of a vector field
-  float2 *basis, *b, *F, *X, *Y;
-  const float2 *A[3], *B[3], *C[3], *T[3];
+  float2 *basis, *b, *F, *X, *Z;
+  const float2 *A[3], *B[3], *C[3], *T[3], *sinv[3];
   double2 *part, *h, *y;
   float2* vec(int i) const { return basis + (long long)i * n3; }
 };
@@ -1851,7 +1852,7 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
   s.b = reinterpret_cast<float2*>(base + S.b);
   s.F = reinterpret_cast<float2*>(base + S.F);
   s.X = reinterpret_cast<float2*>(base + S.X);
-  s.Y = reinterpret_cast<float2*>(base + S.Y);
+  s.Z = reinterpret_cast<float2*>(base + S.Z);
   s.part = reinterpret_cast<double2*>(base + S.part);
   s.h = reinterpret_cast<double2*>(base + S.h);
   s.y = reinterpret_cast<double2*>(base + S.y);
@@ -1863,6 +1864,7 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
     s.B[a] = m + (size_t)n * n;
     s.C[a] = m + 2 * (size_t)n * n;
     s.T[a] = m + 3 * (size_t)n * n;
+    s.sinv[a] = m + 4 * (size_t)n * n;
     hipLaunchKernelGGL(k_scpml_columns, dim3((n + 127) / 128), dim3(128), 0, p->stream, n,
                        p->pml[a], layer->order, layer->alpha_max, col, col + n, col + 2 * n,
                        col + 3 * n, col + 4 * n);
@@ -1871,46 +1873,55 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
     hipLaunchKernelGGL(k_scpml_matrices, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
                        p->stream, n, p->pml[a], col, col + n, col + 2 * n, col + 3 * n,
                        col + 4 * n, const_cast<float2*>(s.A[a]), const_cast<float2*>(s.B[a]),
-                       const_cast<float2*>(s.C[a]), const_cast<float2*>(s.T[a]));
+                       const_cast<float2*>(s.C[a]), const_cast<float2*>(s.T[a]),
+                       const_cast<float2*>(s.sinv[a]));
     HIP_LAUNCHED();
   }
   return CBS_OK;
 }
 
-// out = alpha M in (+ out) along axis `axis` of scalar [nz][ny][nx] fields
+// one axis product (kMm* epilogues, see scpml.hpp) over scalar [nz][ny][nx] fields
 int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in, float2* out,
-                    float alpha, bool accumulate) {
+                    float alpha, bool accumulate, int mode = kMmPlain, float2* out2 = nullptr) {
   AxisMM a;
   a.M = M;
   a.in = in;
   a.out = out;
+  a.out2 = out2;
+  a.sinv = s.sinv[axis];
   a.n = s.dims[axis];
   a.Q = axis == 0 ? 1 : (axis == 1 ? s.dims[0] : s.dims[0] * s.dims[1]);
+  a.p = s.p->pml[axis];
+  a.rows = mode == kMmLayer ? 2 * a.p : a.n;
   a.L = s.N / a.n;
   a.alpha = alpha;
   a.accumulate = accumulate ? 1 : 0;
-  const dim3 grid((unsigned)((a.L + kMmTL - 1) / kMmTL), (unsigned)((a.n + kMmTI - 1) / kMmTI));
+  a.mode = mode;
+  if (a.rows <= 0) return CBS_OK;
+  const dim3 grid((unsigned)((a.L + kMmTL - 1) / kMmTL), (unsigned)((a.rows + kMmTI - 1) / kMmTI));
   hipLaunchKernelGGL(k_axis_mm, grid, dim3(256), 0, s.p->stream, a);
   HIP_LAUNCHED();
   return CBS_OK;
 }
 
 // F = alpha (L_s - L) v:  per component c, sum_{b != c} A_b v_c + B_c v_c +
-// C_c X - T_c Y with X = sum_b C_b v_b, Y = sum_b T_b v_b (an axis without a
-// layer has A = B = 0 exactly and is skipped)
+// T_c Z + (S_c^-1 - I) T_c X, where one product u_b = T_b v_b per axis gives
+// X = sum_b S_b^-1 u_b and Z = sum_b (S_b^-1 - I) u_b, and (S_c^-1 - I) T_c X is
+// formed on the layer rows only (an axis without a layer has A = B = 0 and
+// S^-1 = I exactly and skips those terms)
 int enqueue_delta(const Scpml& s, const float2* v, float2* F, float alpha) {
   const long long N = s.N;
   const int* pml = s.p->pml;
   int rc;
-  for (int b = 0; b < 3; ++b) {
-    if ((rc = enqueue_axis_mm(s, b, s.C[b], v + b * N, s.X, 1.0f, b > 0))) return rc;
-    if ((rc = enqueue_axis_mm(s, b, s.T[b], v + b * N, s.Y, 1.0f, b > 0))) return rc;
-  }
+  for (int b = 0; b < 3; ++b)
+    if ((rc = enqueue_axis_mm(s, b, s.T[b], v + b * N, s.X, 1.0f, b > 0, kMmSplit, s.Z)))
+      return rc;
   for (int c = 0; c < 3; ++c) {
     float2* Fc = F + c * N;
     const float2* vc = v + c * N;
-    if ((rc = enqueue_axis_mm(s, c, s.C[c], s.X, Fc, alpha, false))) return rc;
-    if ((rc = enqueue_axis_mm(s, c, s.T[c], s.Y, Fc, -alpha, true))) return rc;
+    if ((rc = enqueue_axis_mm(s, c, s.T[c], s.Z, Fc, alpha, false))) return rc;
+    if (pml[c] > 0 && (rc = enqueue_axis_mm(s, c, s.T[c], s.X, Fc, alpha, true, kMmLayer)))
+      return rc;
     if (pml[c] > 0 && (rc = enqueue_axis_mm(s, c, s.B[c], vc, Fc, alpha, true))) return rc;
     for (int b = 0; b < 3; ++b)
       if (b != c && pml[b] > 0 && (rc = enqueue_axis_mm(s, b, s.A[b], vc, Fc, alpha, true)))
@@ -1983,9 +1994,10 @@ int read_back(cbs_plan_s* p, const double2* dev, std::complex<double>* host, int
 }
 
 // Restarted GMRES(m) on B x = b from x = 0 (x in E_dev).  Arnoldi with
-// classical Gram-Schmidt applied twice (two fused dot/update passes), Givens
-// rotations on the host in FP64; at the end of each cycle the true residual
-// b - B x gives the restart vector and the reported residual.
+// classical Gram-Schmidt (fused dot and update passes over the basis),
+// repeated for a step whose projection removed more than half of |w|^2;
+// Givens rotations on the host in FP64; at the end of each cycle the true
+// residual b - B x gives the restart vector and the reported residual.
 int scpml_gmres(const Scpml& s, float2* x, int m, const cbs_opts* o, double beta0, int* iters,
                 double* rel_out, std::vector<double>& hist) {
   cbs_plan_s* p = s.p;
@@ -2010,14 +2022,25 @@ int scpml_gmres(const Scpml& s, float2* x, int m, const cbs_opts* o, double beta
       double2* h0 = s.h;
       double2* h1 = s.h + (m + 1);
       double2* h2 = s.h + 2 * (m + 1);
-      if ((rc = enqueue_dots(s, s.basis, j + 1, w, h0))) return rc;
+      // classical Gram-Schmidt; w = V_{j+1}, so one sweep over V_0..V_{j+1}
+      // also gives |w|^2 before the projection (h0[j+1])
+      if ((rc = enqueue_dots(s, s.basis, j + 2, w, h0))) return rc;
       if ((rc = enqueue_update(s, j + 1, h0, -1.0f, w))) return rc;
-      if ((rc = enqueue_dots(s, s.basis, j + 1, w, h1))) return rc;
-      if ((rc = enqueue_update(s, j + 1, h1, -1.0f, w))) return rc;
       if ((rc = enqueue_dots(s, w, 1, w, h2))) return rc;
       if ((rc = read_back(p, s.h, hv.data(), 3 * (m + 1)))) return rc;
-      const double hn = std::sqrt(std::max(0.0, hv[2 * (m + 1)].real()));
-      for (int i = 0; i <= j; ++i) Hij(i, j) = hv[i] + hv[(m + 1) + i];
+      for (int i = 0; i <= j; ++i) Hij(i, j) = hv[i];
+      double nn = hv[2 * (m + 1)].real();
+      // projected away more than half of |w|^2: rounding may have left
+      // components along the basis, so project once more (the DGKS criterion)
+      if (nn < 0.5 * hv[j + 1].real()) {
+        if ((rc = enqueue_dots(s, s.basis, j + 1, w, h1))) return rc;
+        if ((rc = enqueue_update(s, j + 1, h1, -1.0f, w))) return rc;
+        if ((rc = enqueue_dots(s, w, 1, w, h2))) return rc;
+        if ((rc = read_back(p, s.h, hv.data(), 3 * (m + 1)))) return rc;
+        for (int i = 0; i <= j; ++i) Hij(i, j) += hv[(m + 1) + i];
+        nn = hv[2 * (m + 1)].real();
+      }
+      const double hn = std::sqrt(std::max(0.0, nn));
       Hij(j + 1, j) = hn;
       for (int i = 0; i <= j; ++i)
         if (!std::isfinite(Hij(i, j).real()) || !std::isfinite(Hij(i, j).imag()))

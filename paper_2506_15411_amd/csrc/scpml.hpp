@@ -16,11 +16,16 @@
 //
 // every term a 1D operator along one axis.  Each is stored as a dense n x n
 // matrix (built in FP64 on the device from the circulant columns of D, T, D^2,
-// T^2) and applied to all lines of a field by a tiled complex GEMM.  Work is
-// in units of the pitch (p d in [-pi, pi]).
+// T^2) and applied to all lines of a field by a tiled complex GEMM.  Since
+// S^-1 - I vanishes outside the layer, C_c X - T_c Y is evaluated as
+// T_c Z + (S_c^-1 - I) T_c X with Z = X - Y = sum_b (S_b^-1 - I) T_b E_b: one
+// product T_b E_b per axis gives both X and Z, and T_c X is needed on the 2p
+// layer rows only.  Work is in units of the pitch (p d in [-pi, pi]).
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
 
 namespace cbs {
 
@@ -86,15 +91,17 @@ __global__ void k_scpml_columns(int n, int pml, int order, double alpha, double2
 }
 
 // The four n x n operators of one axis, row-major FP32:
-//   A = D^2 - S^-1 D S^-1 D,  B = T^2 - S^-1 T S^-1 T,  C = S^-1 T,  T.
+//   A = D^2 - S^-1 D S^-1 D,  B = T^2 - S^-1 T S^-1 T,  C = S^-1 T,  T,
+// and 1/s in FP32.
 // (S^-1 D S^-1 D)_ij = s_i^-1 (D^2_ij + sum_{k in layer} D_ik (s_k^-1 - 1) D_kj):
 // only layer voxels have s_k != 1.  One thread per entry, FP64.
 __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2* t,
                                  const double2* dd, const double2* tt, const double2* sinv,
-                                 float2* A, float2* B, float2* C, float2* T) {
+                                 float2* A, float2* B, float2* C, float2* T, float2* sinv32) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
+  if (j == 0) sinv32[i] = make_float2((float)sinv[i].x, (float)sinv[i].y);
   const int ij = ((i - j) % n + n) % n;
   double2 sd = make_double2(0, 0), st = make_double2(0, 0);
   auto layer_term = [&](int k) {
@@ -117,19 +124,31 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
   T[e] = make_float2((float)t[ij].x, (float)t[ij].y);
 }
 
-// out(l, i) = alpha sum_j M[i][j] in(l, j)  (+ out(l, i) if accumulate) for every
-// line l of a scalar [nz][ny][nx] field along one axis of length n: element i of
-// line l sits at (l / Q) n Q + l % Q + i Q (Q = 1 along x, nx along y, nx ny
-// along z).  Tiles of 64 lines x 64 outputs, j staged through LDS 16 at a time;
-// each thread accumulates 4 x 4 complex products.
+// Products of one n x n matrix M with every line of a scalar [nz][ny][nx] field
+// along one axis of length n: element i of line l sits at (l / Q) n Q + l % Q
+// + i Q (Q = 1 along x, nx along y, nx ny along z).  With acc(l, i) = sum_j
+// M[i][j] in(l, j), the epilogue is one of
+//   kMmPlain:  out = alpha acc               (+ out if accumulate)
+//   kMmSplit:  out = alpha s_i acc,  out2 = alpha (s_i - 1) acc   (+= each if accumulate)
+//   kMmLayer:  out += alpha (s_i - 1) acc, for the 2p layer rows i only
+// where s_i is 1/s at voxel i of the axis (FP32).  Tiles of 64 lines x 64
+// outputs, j staged through LDS 16 at a time; each thread accumulates 4 x 4
+// complex products.
+enum : int { kMmPlain = 0, kMmSplit = 1, kMmLayer = 2 };
+
 struct AxisMM {
   const float2* M;
   const float2* in;
   float2* out;
+  float2* out2;         // kMmSplit
+  const float2* sinv;   // kMmSplit, kMmLayer: 1/s along the axis
   int n, Q;
-  long long L;      // lines
+  int rows;             // output rows computed: n, or 2p for kMmLayer
+  int p;                // layer voxels per side (kMmLayer)
+  long long L;          // lines
   float alpha;
   int accumulate;
+  int mode;
 };
 
 constexpr int kMmTL = 64, kMmTI = 64, kMmTJ = 16;
@@ -138,12 +157,17 @@ __device__ __forceinline__ long long axis_addr(long long l, int i, int n, int Q)
   return (l / Q) * (long long)n * Q + l % Q + (long long)i * Q;
 }
 
+// output row r of the launch -> row i of the matrix (the layer rows for kMmLayer)
+__device__ __forceinline__ int mm_row(const AxisMM& a, int r) {
+  return (a.mode == kMmLayer && r >= a.p) ? r + (a.n - 2 * a.p) : r;
+}
+
 __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   __shared__ float2 sIn[kMmTJ][kMmTL + 1];
   __shared__ float2 sM[kMmTJ][kMmTI + 1];
   const int tid = threadIdx.x;
   const long long l0 = (long long)blockIdx.x * kMmTL;
-  const int i0 = blockIdx.y * kMmTI;
+  const int r0 = blockIdx.y * kMmTI;
   // along x (Q = 1) consecutive lanes take consecutive outputs i, otherwise
   // consecutive lines (both are contiguous in memory)
   const bool rowwise = a.Q == 1;
@@ -169,8 +193,9 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
     for (int e = 0; e < (kMmTI * kMmTJ) / 256; ++e) {
       const int idx = tid + 256 * e;
       const int jj = idx % kMmTJ, ii = idx / kMmTJ;
-      const int i = i0 + ii, j = j0 + jj;
-      sM[jj][ii] = (i < a.n && j < a.n) ? a.M[(long long)i * a.n + j] : make_float2(0.f, 0.f);
+      const int r = r0 + ii, j = j0 + jj;
+      sM[jj][ii] = (r < a.rows && j < a.n) ? a.M[(long long)mm_row(a, r) * a.n + j]
+                                           : make_float2(0.f, 0.f);
     }
     __syncthreads();
 #pragma unroll 4
@@ -195,16 +220,41 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const long long l = l0 + tl + 16 * r;
-      const int i = i0 + ti + 16 * s;
-      if (l < a.L && i < a.n) {
+      const int rr = r0 + ti + 16 * s;
+      if (l < a.L && rr < a.rows) {
+        const int i = mm_row(a, rr);
         const long long o = axis_addr(l, i, a.n, a.Q);
-        float2 v = make_float2(a.alpha * acc[r][s].x, a.alpha * acc[r][s].y);
-        if (a.accumulate) {
-          const float2 w = a.out[o];
-          v.x += w.x;
-          v.y += w.y;
+        const float2 v = make_float2(a.alpha * acc[r][s].x, a.alpha * acc[r][s].y);
+        if (a.mode == kMmPlain) {
+          float2 w = v;
+          if (a.accumulate) {
+            const float2 u = a.out[o];
+            w.x += u.x;
+            w.y += u.y;
+          }
+          a.out[o] = w;
+        } else {
+          const float2 si = a.sinv[i];
+          const float2 dm = make_float2(si.x - 1.0f, si.y);   // 1/s - 1
+          float2 w2 = cmul(dm, v);
+          if (a.mode == kMmLayer || a.accumulate) {
+            const float2 u = a.mode == kMmLayer ? a.out[o] : a.out2[o];
+            w2.x += u.x;
+            w2.y += u.y;
+          }
+          if (a.mode == kMmLayer) {
+            a.out[o] = w2;
+          } else {
+            float2 w = cmul(si, v);
+            if (a.accumulate) {
+              const float2 u = a.out[o];
+              w.x += u.x;
+              w.y += u.y;
+            }
+            a.out[o] = w;
+            a.out2[o] = w2;
+          }
         }
-        a.out[o] = v;
       }
     }
 }

@@ -71,7 +71,8 @@ def test_equal_gmres_steps_match_oracle(device):
     g = oc.Grid(*shape, LAM / 8, LAM, 1.0, pml, sigma_max=0.0)
     p = plan(shape, pml, device, eps=eps)
     for steps in (8, 16):
-        E, st = p.solve_scpml(alpha_max=1.5, restart=8, tol=0.0, max_iter=steps, scattered=True)
+        E, st = p.solve_scpml(alpha_max=1.5, order=2, restart=8, tol=0.0, max_iter=steps,
+                              scattered=True)
         assert st.status == L.CBS_NOT_CONVERGED and st.iterations == steps
         Eo, res = scpml.gmres_solve(g, eps, oc.plane_wave_source(g, eps), 1.5, rtol=1e-30,
                                     restart=8, maxiter=steps // 8, require_convergence=False)
@@ -90,8 +91,8 @@ def test_converged_matches_dense_lu(device):
     g = oc.Grid(*shape, LAM / 6, LAM, 1.0, pml, sigma_max=0.0)
     Ed = scpml.solve_dense(g, eps, oc.plane_wave_source(g, eps), 2.0)
     p = plan(shape, pml, device, pitch=LAM / 6, eps=eps)
-    E, st = p.solve_scpml(alpha_max=2.0, restart=30, tol=1e-6, max_iter=3000, scattered=True,
-                          history=True)
+    E, st = p.solve_scpml(alpha_max=2.0, order=2, restart=30, tol=1e-6, max_iter=3000,
+                          scattered=True, history=True)
     assert st.status == L.CBS_OK and st.converged and st.residual <= 1e-6
     h = p.history()
     assert len(h) == st.iterations and h[-1] <= 1.5e-6
@@ -99,7 +100,7 @@ def test_converged_matches_dense_lu(device):
     print(f"8x8x12: {st.iterations} steps, residual {st.residual:.2e}, field rel {err:.2e}")
     assert err < 1e-5
     # the total field adds the incident wave
-    Et, _ = p.solve_scpml(alpha_max=2.0, restart=30, tol=1e-6, max_iter=3000)
+    Et, _ = p.solve_scpml(alpha_max=2.0, order=2, restart=30, tol=1e-6, max_iter=3000)
     assert rel(Et.cpu().numpy(), Ed + oc.plane_wave(g)) < 1e-5
     p.close()
 
