@@ -1995,7 +1995,7 @@ int read_back(cbs_plan_s* p, const double2* dev, std::complex<double>* host, int
 
 // Restarted GMRES(m) on B x = b from x = 0 (x in E_dev).  Arnoldi with
 // classical Gram-Schmidt (fused dot and update passes over the basis),
-// repeated for a step whose projection removed more than half of |w|^2;
+// repeated for a step whose projection shortened w more than tenfold;
 // Givens rotations on the host in FP64; at the end of each cycle the true
 // residual b - B x gives the restart vector and the reported residual.
 int scpml_gmres(const Scpml& s, float2* x, int m, const cbs_opts* o, double beta0, int* iters,
@@ -2030,9 +2030,10 @@ int scpml_gmres(const Scpml& s, float2* x, int m, const cbs_opts* o, double beta
       if ((rc = read_back(p, s.h, hv.data(), 3 * (m + 1)))) return rc;
       for (int i = 0; i <= j; ++i) Hij(i, j) = hv[i];
       double nn = hv[2 * (m + 1)].real();
-      // projected away more than half of |w|^2: rounding may have left
-      // components along the basis, so project once more (the DGKS criterion)
-      if (nn < 0.5 * hv[j + 1].real()) {
+      // the projection shortened w more than tenfold: FP32 rounding of the
+      // update may have left components along the basis of about 10 ulp of the
+      // original length, so project once more (a DGKS-type test)
+      if (nn < 1e-2 * hv[j + 1].real()) {
         if ((rc = enqueue_dots(s, s.basis, j + 1, w, h1))) return rc;
         if ((rc = enqueue_update(s, j + 1, h1, -1.0f, w))) return rc;
         if ((rc = enqueue_dots(s, w, 1, w, h2))) return rc;
