@@ -111,7 +111,7 @@ def gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: float = 
 
 def cbs_gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: float = 1e-10,
                     restart: int = 20, maxiter: int = 2000, x0: np.ndarray | None = None,
-                    callback=None) -> np.ndarray:
+                    callback=None, require_convergence: bool = True) -> np.ndarray:
     """E_s = A^-1 S by FP64 GMRES on the preconditioned system of the CBS
     iteration (references [25], [26]).  The CBS step E <- E + gamma (G (V E + S) - E)
     has the fixed point of
@@ -122,7 +122,9 @@ def cbs_gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: floa
     kb^2 - i eps, so (L - kb^2 - i eps)(I - G V) = L - K = A); GMRES on it reaches
     the same solution as the iteration without its slow tail.  rtol is the
     relative residual of this preconditioned system; x0 is an initial E_s (for
-    instance a CBS iterate).  callback(k, residual) is called every inner step."""
+    instance a CBS iterate).  callback(k, residual) is called every inner step.
+    With require_convergence=False the iterate after maxiter restart cycles is
+    returned even if rtol was not met."""
     pot = _cbs.potentials(g, eps_r)
     shp = (3,) + g.vshape
     N3 = 3 * g.n_vox
@@ -145,6 +147,6 @@ def cbs_gmres_solve(g: "_cbs.Grid", eps_r: np.ndarray, S: np.ndarray, rtol: floa
     x, info = spla.gmres(M, b, x0=None if x0 is None else np.asarray(x0).reshape(-1),
                          rtol=rtol, atol=0.0, restart=restart, maxiter=maxiter,
                          callback=cb, callback_type="pr_norm")
-    if info != 0:
+    if info != 0 and require_convergence:
         raise RuntimeError(f"GMRES did not converge (info={info})")
     return x.reshape(shp)
