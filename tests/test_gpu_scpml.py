@@ -84,6 +84,39 @@ def test_equal_gmres_steps_match_oracle(device):
     p.close()
 
 
+@pytest.mark.parametrize("kind", ["oblique plane wave", "point source"])
+def test_other_sources_at_equal_gmres_steps(kind, device):
+    """The stretched-layer solve with an oblique p-polarised plane wave and with
+    a point source (every source kind goes through the same first CBS step),
+    12 GMRES(6) steps against the oracle's GMRES on the same source."""
+    shape, pml = (24, 20, 32), (3, 3, 4)
+    eps = scenes.random_passive_eps(shape, pml, 133, loss=0.02)
+    g = oc.Grid(*shape, LAM / 8, LAM, 1.0, pml, sigma_max=0.0)
+    p = plan(shape, pml, device, eps=eps)
+    if kind == "point source":
+        r0, amp = (11, 9, 17), (g.k0 ** 2, 0.5j * g.k0 ** 2, 0.0)
+        S = oc.point_source(g, r0, amp)
+        E, st = p.solve_scpml(alpha_max=0.75, order=1, restart=6, tol=0.0, max_iter=12,
+                              point=(r0, amp))
+    else:
+        d = (0.3, 0.2)
+        sx, sy = d
+        cz, st_ = np.sqrt(1 - sx * sx - sy * sy), np.hypot(sx, sy)
+        pol = (cz * sx / st_, cz * sy / st_, -st_)
+        S = oc.plane_wave_source(g, eps, pol, d)
+        E, st = p.solve_scpml(alpha_max=0.75, order=1, restart=6, tol=0.0, max_iter=12,
+                              scattered=True, pol=pol, direction=d)
+    assert st.status == L.CBS_NOT_CONVERGED and st.iterations == 12
+    Eo, res = scpml.gmres_solve(g, eps, S, 0.75, 1, rtol=1e-30, restart=6, maxiter=2,
+                                require_convergence=False)
+    err = rel(E.cpu().numpy(), Eo)
+    print(f"{kind}: 12 GMRES steps, field rel {err:.2e}, residual gpu {st.residual:.4e} "
+          f"oracle {res:.4e}")
+    assert err < 1e-5
+    assert abs(st.residual - res) < 1e-4 * res
+    p.close()
+
+
 def test_converged_matches_dense_lu(device):
     shape, pml = (8, 8, 12), (2, 2, 3)
     eps = np.ones(shape[::-1], dtype=np.float32)
