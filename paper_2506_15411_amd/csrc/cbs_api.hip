@@ -1898,8 +1898,9 @@ int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in,
   a.accumulate = accumulate ? 1 : 0;
   a.mode = mode;
   if (a.rows <= 0) return CBS_OK;
-  const dim3 grid((unsigned)((a.L + kMmTL - 1) / kMmTL), (unsigned)((a.rows + kMmTI - 1) / kMmTI));
-  hipLaunchKernelGGL(k_axis_mm, grid, dim3(256), 0, s.p->stream, a);
+  const unsigned tiles = (unsigned)((a.L + kMmTL - 1) / kMmTL) *
+                         (unsigned)((a.rows + kMmTI - 1) / kMmTI);
+  hipLaunchKernelGGL(k_axis_mm, dim3(tiles), dim3(256), 0, s.p->stream, a);
   HIP_LAUNCHED();
   return CBS_OK;
 }

@@ -132,8 +132,7 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
 //   kMmSplit:  out = alpha s_i acc,  out2 = alpha (s_i - 1) acc   (+= each if accumulate)
 //   kMmLayer:  out += alpha (s_i - 1) acc, for the 2p layer rows i only
 // where s_i is 1/s at voxel i of the axis (FP32).  Tiles of 64 lines x 64
-// outputs, j staged through LDS 16 at a time; each thread accumulates 4 x 4
-// complex products.
+// outputs, j staged through LDS 16 at a time.
 enum : int { kMmPlain = 0, kMmSplit = 1, kMmLayer = 2 };
 
 struct AxisMM {
@@ -151,7 +150,7 @@ struct AxisMM {
   int mode;
 };
 
-constexpr int kMmTL = 64, kMmTI = 64, kMmTJ = 16;
+constexpr int kMmTL = 64, kMmTI = 64, kMmTJ = 32;
 
 __device__ __forceinline__ long long axis_addr(long long l, int i, int n, int Q) {
   return (l / Q) * (long long)n * Q + l % Q + (long long)i * Q;
@@ -162,101 +161,150 @@ __device__ __forceinline__ int mm_row(const AxisMM& a, int r) {
   return (a.mode == kMmLayer && r >= a.p) ? r + (a.n - 2 * a.p) : r;
 }
 
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+// The complex products run on the FP32 matrix cores: v_mfma_f32_16x16x4_f32
+// multiplies a 16 x 4 block A (lane l holds A[l % 16][l / 16]) by a 4 x 16 block
+// B (lane l holds B[l / 16][l % 16]) into a 16 x 16 block D (lane l holds
+// D[4 (l / 16) + r][l % 16] in register r).  A complex block product takes four:
+// Re += Mr Xr - Mi Xi, Im += Mr Xi + Mi Xr.  Each of the four waves of a
+// work-group owns a 32 x 32 part of the 64 x 64 output tile (2 x 2 blocks).
 __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   __shared__ float2 sIn[kMmTJ][kMmTL + 1];
   __shared__ float2 sM[kMmTJ][kMmTI + 1];
   const int tid = threadIdx.x;
-  const long long l0 = (long long)blockIdx.x * kMmTL;
-  const int r0 = blockIdx.y * kMmTI;
-  // along x (Q = 1) consecutive lanes take consecutive outputs i, otherwise
-  // consecutive lines (both are contiguous in memory)
+  // block -> (line tile, row tile) with the row tiles of one line tile adjacent
+  // in the XCD-remapped order, so the line tile they all read stays in one L2
+  const unsigned rtiles = (unsigned)((a.rows + kMmTI - 1) / kMmTI);
+  const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
+  const long long l0 = (long long)(Lb / rtiles) * kMmTL;
+  const int r0 = (int)(Lb % rtiles) * kMmTI;
+  // the global loads: along x (Q = 1) a line's elements j are contiguous,
+  // otherwise consecutive lines are
   const bool rowwise = a.Q == 1;
-  const int tl = rowwise ? tid / 16 : tid % 16;
-  const int ti = rowwise ? tid % 16 : tid / 16;
-  float2 acc[4][4];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave & 1) * 32, wl = (wave >> 1) * 32;   // this wave's rows i, lines l
+  const int lr = lane & 15, lk = lane >> 4;
+  mfma_f4 accr[2][2], acci[2][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc[r][s] = make_float2(0.f, 0.f);
+    for (int lb = 0; lb < 2; ++lb) {
+      accr[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      acci[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+    }
 
-  for (int j0 = 0; j0 < a.n; j0 += kMmTJ) {
+  // the next stage's tiles are fetched into registers while the matrix cores
+  // work on the current one
+  constexpr int kIn = (kMmTL * kMmTJ) / 256, kMt = (kMmTI * kMmTJ) / 256;
+  float2 pin[kIn], pm[kMt];
+  auto fetch = [&](int j0) {
 #pragma unroll
-    for (int e = 0; e < (kMmTL * kMmTJ) / 256; ++e) {
+    for (int e = 0; e < kIn; ++e) {
       const int idx = tid + 256 * e;
       const int jj = rowwise ? idx % kMmTJ : idx / kMmTL;
       const int ll = rowwise ? idx / kMmTJ : idx % kMmTL;
       const long long l = l0 + ll;
       const int j = j0 + jj;
-      sIn[jj][ll] = (l < a.L && j < a.n) ? a.in[axis_addr(l, j, a.n, a.Q)] : make_float2(0.f, 0.f);
+      pin[e] = (l < a.L && j < a.n) ? a.in[axis_addr(l, j, a.n, a.Q)] : make_float2(0.f, 0.f);
     }
 #pragma unroll
-    for (int e = 0; e < (kMmTI * kMmTJ) / 256; ++e) {
+    for (int e = 0; e < kMt; ++e) {
       const int idx = tid + 256 * e;
       const int jj = idx % kMmTJ, ii = idx / kMmTJ;
       const int r = r0 + ii, j = j0 + jj;
-      sM[jj][ii] = (r < a.rows && j < a.n) ? a.M[(long long)mm_row(a, r) * a.n + j]
-                                           : make_float2(0.f, 0.f);
+      pm[e] = (r < a.rows && j < a.n) ? a.M[(long long)mm_row(a, r) * a.n + j]
+                                      : make_float2(0.f, 0.f);
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int e = 0; e < kIn; ++e) {
+      const int idx = tid + 256 * e;
+      const int jj = rowwise ? idx % kMmTJ : idx / kMmTL;
+      const int ll = rowwise ? idx / kMmTJ : idx % kMmTL;
+      sIn[jj][ll] = pin[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kMt; ++e) {
+      const int idx = tid + 256 * e;
+      sM[idx % kMmTJ][idx / kMmTJ] = pm[e];
+    }
+  };
+  fetch(0);
+  for (int j0 = 0; j0 < a.n; j0 += kMmTJ) {
+    stash();
     __syncthreads();
-#pragma unroll 4
-    for (int jj = 0; jj < kMmTJ; ++jj) {
-      float2 b[4], m[4];
+    if (j0 + kMmTJ < a.n) fetch(j0 + kMmTJ);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) b[r] = sIn[jj][tl + 16 * r];
+    for (int ks = 0; ks < kMmTJ / 4; ++ks) {
+      const int k = 4 * ks + lk;
+      float2 am[2], bx[2];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) m[s] = sM[jj][ti + 16 * s];
+      for (int ib = 0; ib < 2; ++ib) am[ib] = sM[k][wi + 16 * ib + lr];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int lb = 0; lb < 2; ++lb) bx[lb] = sIn[k][wl + 16 * lb + lr];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          acc[r][s].x = fmaf(m[s].x, b[r].x, fmaf(-m[s].y, b[r].y, acc[r][s].x));
-          acc[r][s].y = fmaf(m[s].x, b[r].y, fmaf(m[s].y, b[r].x, acc[r][s].y));
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int lb = 0; lb < 2; ++lb) {
+          accr[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].x, bx[lb].x, accr[ib][lb], 0, 0, 0);
+          acci[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].x, bx[lb].y, acci[ib][lb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+        for (int lb = 0; lb < 2; ++lb) {
+          accr[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-am[ib].y, bx[lb].y, accr[ib][lb], 0, 0, 0);
+          acci[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].y, bx[lb].x, acci[ib][lb], 0, 0, 0);
         }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
+  for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const long long l = l0 + tl + 16 * r;
-      const int rr = r0 + ti + 16 * s;
-      if (l < a.L && rr < a.rows) {
-        const int i = mm_row(a, rr);
-        const long long o = axis_addr(l, i, a.n, a.Q);
-        const float2 v = make_float2(a.alpha * acc[r][s].x, a.alpha * acc[r][s].y);
-        if (a.mode == kMmPlain) {
-          float2 w = v;
-          if (a.accumulate) {
-            const float2 u = a.out[o];
-            w.x += u.x;
-            w.y += u.y;
-          }
-          a.out[o] = w;
-        } else {
-          const float2 si = a.sinv[i];
-          const float2 dm = make_float2(si.x - 1.0f, si.y);   // 1/s - 1
-          float2 w2 = cmul(dm, v);
-          if (a.mode == kMmLayer || a.accumulate) {
-            const float2 u = a.mode == kMmLayer ? a.out[o] : a.out2[o];
-            w2.x += u.x;
-            w2.y += u.y;
-          }
-          if (a.mode == kMmLayer) {
-            a.out[o] = w2;
-          } else {
-            float2 w = cmul(si, v);
+    for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long l = l0 + wl + 16 * lb + lr;
+        const int rr = r0 + wi + 16 * ib + 4 * lk + q;
+        if (l < a.L && rr < a.rows) {
+          const int i = mm_row(a, rr);
+          const long long o = axis_addr(l, i, a.n, a.Q);
+          const float2 v = make_float2(a.alpha * accr[ib][lb][q], a.alpha * acci[ib][lb][q]);
+          if (a.mode == kMmPlain) {
+            float2 w = v;
             if (a.accumulate) {
               const float2 u = a.out[o];
               w.x += u.x;
               w.y += u.y;
             }
             a.out[o] = w;
-            a.out2[o] = w2;
+          } else {
+            const float2 si = a.sinv[i];
+            const float2 dm = make_float2(si.x - 1.0f, si.y);   // 1/s - 1
+            float2 w2 = cmul(dm, v);
+            if (a.mode == kMmLayer || a.accumulate) {
+              const float2 u = a.mode == kMmLayer ? a.out[o] : a.out2[o];
+              w2.x += u.x;
+              w2.y += u.y;
+            }
+            if (a.mode == kMmLayer) {
+              a.out[o] = w2;
+            } else {
+              float2 w = cmul(si, v);
+              if (a.accumulate) {
+                const float2 u = a.out[o];
+                w.x += u.x;
+                w.y += u.y;
+              }
+              a.out[o] = w;
+              a.out2[o] = w2;
+            }
           }
         }
       }
-    }
 }
 
 // ---------------------------------------------------------------------------
