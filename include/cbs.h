@@ -255,7 +255,7 @@ typedef struct {
 
 /* Device bytes of the stretched-layer workspace: restart + 1 basis fields, the
  * right-hand side, the stretched-derivative source, two scalar fields, the dense
- * per-axis operators (4 n_a^2 complex64 per axis) and reduction buffers.  0 if
+ * per-axis operators (3 n_a^2 complex64 per axis) and reduction buffers.  0 if
  * the grid is not supported, an axis exceeds 1024 or restart is out of range. */
 size_t cbs_scpml_workspace_bytes(int nx, int ny, int nz, int restart);
 

@@ -1807,7 +1807,7 @@ bool scpml_layout(int nx, int ny, int nz, int restart, ScpmlLayout& S) {
   S.X = take(N * sizeof(float2));
   S.Z = take(N * sizeof(float2));
   for (int a = 0; a < 3; ++a)
-    S.mats[a] = take((4 * (size_t)dims[a] * dims[a] + dims[a]) * sizeof(float2));
+    S.mats[a] = take((3 * (size_t)dims[a] * dims[a] + dims[a]) * sizeof(float2));
   for (int a = 0; a < 3; ++a) S.cols[a] = take(5 * (size_t)dims[a] * sizeof(double2));
   S.part = take((size_t)(kScpmlMaxRestart + 1) * kGmBlocks * sizeof(double2));
   S.h = take((size_t)3 * (kScpmlMaxRestart + 1) * sizeof(double2));
@@ -1821,7 +1821,7 @@ struct Scpml {
   int dims[3];
   long long N, n3;            // voxels; complex values of a vector field
   float2 *basis, *b, *F, *X, *Z;
-  const float2 *A[3], *B[3], *C[3], *T[3], *sinv[3];
+  const float2 *A[3], *B[3], *T[3], *sinv[3];
   double2 *part, *h, *y;
   float2* vec(int i) const { return basis + (long long)i * n3; }
 };
@@ -1862,9 +1862,8 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
     double2* col = reinterpret_cast<double2*>(base + S.cols[a]);
     s.A[a] = m;
     s.B[a] = m + (size_t)n * n;
-    s.C[a] = m + 2 * (size_t)n * n;
-    s.T[a] = m + 3 * (size_t)n * n;
-    s.sinv[a] = m + 4 * (size_t)n * n;
+    s.T[a] = m + 2 * (size_t)n * n;
+    s.sinv[a] = m + 3 * (size_t)n * n;
     hipLaunchKernelGGL(k_scpml_columns, dim3((n + 127) / 128), dim3(128), 0, p->stream, n,
                        p->pml[a], layer->order, layer->alpha_max, col, col + n, col + 2 * n,
                        col + 3 * n, col + 4 * n);
@@ -1873,8 +1872,7 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
     hipLaunchKernelGGL(k_scpml_matrices, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0,
                        p->stream, n, p->pml[a], col, col + n, col + 2 * n, col + 3 * n,
                        col + 4 * n, const_cast<float2*>(s.A[a]), const_cast<float2*>(s.B[a]),
-                       const_cast<float2*>(s.C[a]), const_cast<float2*>(s.T[a]),
-                       const_cast<float2*>(s.sinv[a]));
+                       const_cast<float2*>(s.T[a]), const_cast<float2*>(s.sinv[a]));
     HIP_LAUNCHED();
   }
   return CBS_OK;

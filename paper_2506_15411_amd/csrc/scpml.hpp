@@ -90,14 +90,14 @@ __global__ void k_scpml_columns(int n, int pml, int order, double alpha, double2
   sinv[m] = make_double2(1.0 / (1.0 + a * a), -a / (1.0 + a * a));
 }
 
-// The four n x n operators of one axis, row-major FP32:
-//   A = D^2 - S^-1 D S^-1 D,  B = T^2 - S^-1 T S^-1 T,  C = S^-1 T,  T,
-// and 1/s in FP32.
+// The three n x n operators of one axis, row-major FP32:
+//   A = D^2 - S^-1 D S^-1 D,  B = T^2 - S^-1 T S^-1 T,  T,
+// and 1/s in FP32 (C = S^-1 T is applied as 1/s times the T product).
 // (S^-1 D S^-1 D)_ij = s_i^-1 (D^2_ij + sum_{k in layer} D_ik (s_k^-1 - 1) D_kj):
 // only layer voxels have s_k != 1.  One thread per entry, FP64.
 __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2* t,
                                  const double2* dd, const double2* tt, const double2* sinv,
-                                 float2* A, float2* B, float2* C, float2* T, float2* sinv32) {
+                                 float2* A, float2* B, float2* T, float2* sinv32) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (long long)n * n) return;
   const int i = (int)(e / n), j = (int)(e % n);
@@ -117,10 +117,8 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
   const double2 si = sinv[i];
   const double2 a = zsub(dd[ij], zmul(si, zadd(dd[ij], sd)));
   const double2 b = zsub(tt[ij], zmul(si, zadd(tt[ij], st)));
-  const double2 c = zmul(si, t[ij]);
   A[e] = make_float2((float)a.x, (float)a.y);
   B[e] = make_float2((float)b.x, (float)b.y);
-  C[e] = make_float2((float)c.x, (float)c.y);
   T[e] = make_float2((float)t[ij].x, (float)t[ij].y);
 }
 

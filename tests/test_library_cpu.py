@@ -109,12 +109,12 @@ def test_static_solve_checks_before_any_device_call(lib):
 
 def test_stretched_layer_workspace_bytes(lib):
     """cbs_scpml_workspace_bytes is host arithmetic: restart + 4 vector fields,
-    two scalar fields and 4 n^2 complex64 per axis, or 0 out of range."""
+    two scalar fields and 3 n^2 complex64 per axis, or 0 out of range."""
     nx, ny, nz = 24, 20, 32
     n = nx * ny * nz
     b1 = L.cbs_scpml_workspace_bytes(nx, ny, nz, 1)
     b40 = L.cbs_scpml_workspace_bytes(nx, ny, nz, 40)
-    assert b1 >= (2 + 2) * 3 * n * 8 + 2 * n * 8 + 4 * 8 * (nx * nx + ny * ny + nz * nz)
+    assert b1 >= (2 + 2) * 3 * n * 8 + 2 * n * 8 + 3 * 8 * (nx * nx + ny * ny + nz * nz)
     assert b40 - b1 >= 39 * 3 * n * 8
     assert L.cbs_scpml_workspace_bytes(nx, ny, nz, 0) == 0
     assert L.cbs_scpml_workspace_bytes(nx, ny, nz, 65) == 0
