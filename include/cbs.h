@@ -233,8 +233,8 @@ int cbs_solve_batch(cbs_plan_t plan, int count, const cbs_source* srcs, void* E_
 int cbs_batch_step(cbs_plan_t* plans, int count, int iters, int* done_out);
 
 /* ---- stretched-coordinate absorbing layer -------------------------------
- * The paper's absorbing layer is a "perfectly matching" one after reference
- * [31] (simulation-setup paragraph), a stretched-coordinate PML.  Here every
+ * The paper bounds its volume with a perfectly matched layer after its
+ * reference [31] (simulation-setup paragraph), a stretched-coordinate PML.  Here every
  * derivative d/da inside the layer of axis a becomes (1/s_a) d/da with
  * s_a = 1 + i alpha_max u_a^order (u_a the depth into the layer in units of its
  * thickness, outermost voxel u = 1, the same u as the graded potential's), on the

@@ -1,9 +1,9 @@
 """Stretched-coordinate PML (reference [31]) for the spectral vector Helmholtz
 operator.  TEST INFRASTRUCTURE ONLY.
 
-The paper surrounds its volume with a "perfectly matching absorbing layer of
-thickness [lambda, lambda, 6 lambda]" and cites Shin and Fan's comparison of
-PML formulations [31] (setup paragraph).  A stretched-coordinate PML replaces
+The paper's simulation volume is bounded by an absorbing layer, lambda thick
+on the lateral axes and 6 lambda along z in total, of the perfectly matched kind
+compared by its reference [31] (setup paragraph).  A stretched-coordinate PML replaces
 every derivative d/da by (1/s_a(a)) d/da, with s_a = 1 + i alpha_a(a) inside the
 layer of axis a and 1 elsewhere, so an outgoing wave exp(i k a) continues as
 exp(i k a - k integral alpha) and decays without (in the continuum) reflecting.
