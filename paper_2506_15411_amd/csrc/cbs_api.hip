@@ -1898,7 +1898,10 @@ int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in,
   if (a.rows <= 0) return CBS_OK;
   const unsigned tiles = (unsigned)((a.L + kMmTL - 1) / kMmTL) *
                          (unsigned)((a.rows + kMmTI - 1) / kMmTI);
-  hipLaunchKernelGGL(k_axis_mm, dim3(tiles), dim3(256), 0, s.p->stream, a);
+  if (a.Q == 1)
+    hipLaunchKernelGGL(k_axis_mm<true>, dim3(tiles), dim3(256), 0, s.p->stream, a);
+  else
+    hipLaunchKernelGGL(k_axis_mm<false>, dim3(tiles), dim3(256), 0, s.p->stream, a);
   HIP_LAUNCHED();
   return CBS_OK;
 }

@@ -130,7 +130,7 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
 //   kMmSplit:  out = alpha s_i acc,  out2 = alpha (s_i - 1) acc   (+= each if accumulate)
 //   kMmLayer:  out += alpha (s_i - 1) acc, for the 2p layer rows i only
 // where s_i is 1/s at voxel i of the axis (FP32).  Tiles of 64 lines x 64
-// outputs, j staged through LDS 16 at a time.
+// outputs, j staged through LDS 32 at a time.
 enum : int { kMmPlain = 0, kMmSplit = 1, kMmLayer = 2 };
 
 struct AxisMM {
@@ -164,9 +164,13 @@ typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 // The complex products run on the FP32 matrix cores: v_mfma_f32_16x16x4_f32
 // multiplies a 16 x 4 block A (lane l holds A[l % 16][l / 16]) by a 4 x 16 block
 // B (lane l holds B[l / 16][l % 16]) into a 16 x 16 block D (lane l holds
-// D[4 (l / 16) + r][l % 16] in register r).  A complex block product takes four:
-// Re += Mr Xr - Mi Xi, Im += Mr Xi + Mi Xr.  Each of the four waves of a
-// work-group owns a 32 x 32 part of the 64 x 64 output tile (2 x 2 blocks).
+// D[4 (l / 16) + r][l % 16] in register r).  A complex block product takes three
+// (Gauss's form): P1 += Mr Xr, P2 += Mi Xi, P3 += (Mr + Mi)(Xr + Xi), and then
+// Re = P1 - P2, Im = P3 - P1 - P2.  Each of the four waves of a work-group owns
+// a 32 x 32 part of the 64 x 64 output tile (2 x 2 blocks).  ROWWISE (Q = 1,
+// the x axis): a line's elements j are contiguous in memory; otherwise
+// consecutive lines are, and the loads run along the lines.
+template <bool ROWWISE>
 __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   __shared__ float2 sIn[kMmTJ][kMmTL + 1];
   __shared__ float2 sM[kMmTJ][kMmTI + 1];
@@ -177,50 +181,69 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   const unsigned Lb = xcd_remap(blockIdx.x, gridDim.x);
   const long long l0 = (long long)(Lb / rtiles) * kMmTL;
   const int r0 = (int)(Lb % rtiles) * kMmTI;
-  // the global loads: along x (Q = 1) a line's elements j are contiguous,
-  // otherwise consecutive lines are
-  const bool rowwise = a.Q == 1;
   const int lane = tid & 63, wave = tid >> 6;
   const int wi = (wave & 1) * 32, wl = (wave >> 1) * 32;   // this wave's rows i, lines l
   const int lr = lane & 15, lk = lane >> 4;
-  mfma_f4 accr[2][2], acci[2][2];
+  mfma_f4 p1[2][2], p2[2][2], p3[2][2];
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
     for (int lb = 0; lb < 2; ++lb) {
-      accr[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
-      acci[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      p1[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      p2[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
+      p3[ib][lb] = mfma_f4{0.f, 0.f, 0.f, 0.f};
     }
 
   // the next stage's tiles are fetched into registers while the matrix cores
   // work on the current one
   constexpr int kIn = (kMmTL * kMmTJ) / 256, kMt = (kMmTI * kMmTJ) / 256;
   float2 pin[kIn], pm[kMt];
+  // input element e of this thread (idx = tid + 256 e): along x, line
+  // tl + 8 e at j0 + tj; otherwise line tl (the same for every e) at
+  // j0 + tj + 4 e.  The line's base address is formed once, outside the loop.
+  // Loads are unconditional: an element outside the field or the matrix reads
+  // element 0 instead and is replaced by zero.
+  constexpr int kLineStep = 256 / kMmTJ, kJStep = 256 / kMmTL;
+  const int tj = ROWWISE ? tid % kMmTJ : tid / kMmTL;
+  const long long tl = l0 + (ROWWISE ? tid / kMmTJ : tid % kMmTL);
+  const long long lbase = ROWWISE ? tl * a.n : axis_addr(tl, 0, a.n, a.Q);
+  unsigned lok = 0;   // bit e: the line of input element e exists
+#pragma unroll
+  for (int e = 0; e < kIn; ++e)
+    if ((ROWWISE ? tl + kLineStep * e : tl) < a.L) lok |= 1u << e;
+  const int ti = tid / kMmTJ, tjm = tid % kMmTJ;   // matrix element e: row r0 + ti + 8 e
+  long long mrow[kMt];
+  unsigned rok = 0;
+#pragma unroll
+  for (int e = 0; e < kMt; ++e) {
+    const int r = r0 + ti + kLineStep * e;
+    mrow[e] = (long long)mm_row(a, r < a.rows ? r : 0) * a.n;
+    if (r < a.rows) rok |= 1u << e;
+  }
   auto fetch = [&](int j0) {
 #pragma unroll
     for (int e = 0; e < kIn; ++e) {
-      const int idx = tid + 256 * e;
-      const int jj = rowwise ? idx % kMmTJ : idx / kMmTL;
-      const int ll = rowwise ? idx / kMmTJ : idx % kMmTL;
-      const long long l = l0 + ll;
-      const int j = j0 + jj;
-      pin[e] = (l < a.L && j < a.n) ? a.in[axis_addr(l, j, a.n, a.Q)] : make_float2(0.f, 0.f);
+      const int j = ROWWISE ? j0 + tj : j0 + tj + kJStep * e;
+      const bool ok = ((lok >> e) & 1u) && j < a.n;
+      const long long ad = ROWWISE ? lbase + (long long)(kLineStep * e) * a.n + j
+                                   : lbase + (long long)j * a.Q;
+      const float2 v = a.in[ok ? ad : 0];
+      pin[e] = ok ? v : make_float2(0.f, 0.f);
     }
+    const int jm = j0 + tjm;
 #pragma unroll
     for (int e = 0; e < kMt; ++e) {
-      const int idx = tid + 256 * e;
-      const int jj = idx % kMmTJ, ii = idx / kMmTJ;
-      const int r = r0 + ii, j = j0 + jj;
-      pm[e] = (r < a.rows && j < a.n) ? a.M[(long long)mm_row(a, r) * a.n + j]
-                                      : make_float2(0.f, 0.f);
+      const bool ok = ((rok >> e) & 1u) && jm < a.n;
+      const float2 v = a.M[ok ? mrow[e] + jm : 0];
+      pm[e] = ok ? v : make_float2(0.f, 0.f);
     }
   };
   auto stash = [&]() {
 #pragma unroll
     for (int e = 0; e < kIn; ++e) {
       const int idx = tid + 256 * e;
-      const int jj = rowwise ? idx % kMmTJ : idx / kMmTL;
-      const int ll = rowwise ? idx / kMmTJ : idx % kMmTL;
+      const int jj = ROWWISE ? idx % kMmTJ : idx / kMmTL;
+      const int ll = ROWWISE ? idx / kMmTJ : idx % kMmTL;
       sIn[jj][ll] = pin[e];
     }
 #pragma unroll
@@ -238,27 +261,31 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
     for (int ks = 0; ks < kMmTJ / 4; ++ks) {
       const int k = 4 * ks + lk;
       float2 am[2], bx[2];
+      float ams[2], bxs[2];
 #pragma unroll
-      for (int ib = 0; ib < 2; ++ib) am[ib] = sM[k][wi + 16 * ib + lr];
+      for (int ib = 0; ib < 2; ++ib) {
+        am[ib] = sM[k][wi + 16 * ib + lr];
+        ams[ib] = am[ib].x + am[ib].y;
+      }
 #pragma unroll
-      for (int lb = 0; lb < 2; ++lb) bx[lb] = sIn[k][wl + 16 * lb + lr];
+      for (int lb = 0; lb < 2; ++lb) {
+        bx[lb] = sIn[k][wl + 16 * lb + lr];
+        bxs[lb] = bx[lb].x + bx[lb].y;
+      }
 #pragma unroll
       for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
         for (int lb = 0; lb < 2; ++lb) {
-          accr[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].x, bx[lb].x, accr[ib][lb], 0, 0, 0);
-          acci[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].x, bx[lb].y, acci[ib][lb], 0, 0, 0);
-        }
-#pragma unroll
-      for (int ib = 0; ib < 2; ++ib)
-#pragma unroll
-        for (int lb = 0; lb < 2; ++lb) {
-          accr[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-am[ib].y, bx[lb].y, accr[ib][lb], 0, 0, 0);
-          acci[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].y, bx[lb].x, acci[ib][lb], 0, 0, 0);
+          p1[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].x, bx[lb].x, p1[ib][lb], 0, 0, 0);
+          p2[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(am[ib].y, bx[lb].y, p2[ib][lb], 0, 0, 0);
+          p3[ib][lb] = __builtin_amdgcn_mfma_f32_16x16x4f32(ams[ib], bxs[lb], p3[ib][lb], 0, 0, 0);
         }
     }
     __syncthreads();
   }
+  long long obase[2];
+#pragma unroll
+  for (int lb = 0; lb < 2; ++lb) obase[lb] = axis_addr(l0 + wl + 16 * lb + lr, 0, a.n, a.Q);
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -269,8 +296,10 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
         const int rr = r0 + wi + 16 * ib + 4 * lk + q;
         if (l < a.L && rr < a.rows) {
           const int i = mm_row(a, rr);
-          const long long o = axis_addr(l, i, a.n, a.Q);
-          const float2 v = make_float2(a.alpha * accr[ib][lb][q], a.alpha * acci[ib][lb][q]);
+          const long long o = obase[lb] + (long long)i * a.Q;
+          const float re = p1[ib][lb][q] - p2[ib][lb][q];
+          const float im = p3[ib][lb][q] - p1[ib][lb][q] - p2[ib][lb][q];
+          const float2 v = make_float2(a.alpha * re, a.alpha * im);
           if (a.mode == kMmPlain) {
             float2 w = v;
             if (a.accumulate) {
