@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   // j0 + tj + 4 e.  The line's base address is formed once, outside the loop.
   // Loads are unconditional: an element outside the field or the matrix reads
   // element 0 instead and is replaced by zero.
-  constexpr int kLineStep = 256 / kMmTJ, kJStep = 256 / kMmTL;
+  constexpr int kLineStep = 256 / kMmTJ, kJStep = 256 / kMmTL, kRowStep = 256 / kMmTJ;
   const int tj = ROWWISE ? tid % kMmTJ : tid / kMmTL;
   const long long tl = l0 + (ROWWISE ? tid / kMmTJ : tid % kMmTL);
   const long long lbase = ROWWISE ? tl * a.n : axis_addr(tl, 0, a.n, a.Q);
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   unsigned rok = 0;
 #pragma unroll
   for (int e = 0; e < kMt; ++e) {
-    const int r = r0 + ti + kLineStep * e;
+    const int r = r0 + ti + kRowStep * e;
     mrow[e] = (long long)mm_row(a, r < a.rows ? r : 0) * a.n;
     if (r < a.rows) rok |= 1u << e;
   }
