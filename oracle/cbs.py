@@ -237,16 +237,25 @@ def ifftn3(f: np.ndarray) -> np.ndarray:
     return sfft.ifftn(f, axes=(-3, -2, -1), workers=_WORKERS)
 
 
-def green_apply(g: Grid, W: np.ndarray, kt2: complex) -> np.ndarray:
-    """G W = F^-1 [G^(p) . F W]  for a vector field W [3, nz, ny, nx].
-
-    Applies the 3x3 Sherman-Morrison tensor mode by mode (same formula as
-    ``green_tensor``, written out on the broadcast grid)."""
+def green_factors(g: Grid, kt2: complex):
+    """The mode-wise scalars of the Sherman-Morrison form of G^(p) on the
+    broadcast grid: pt, a = 1 / (p^2 - kt2) and b = 1 / (p^2 - |pt|^2 - kt2).
+    They depend on the grid and kt2 only, so a solve forms them once."""
     (pz, py, px), (ptz, pty, ptx) = fourier_grid(g)
     p2 = px * px + py * py + pz * pz
     pt2 = ptx * ptx + pty * pty + ptz * ptz
     a = 1.0 / (p2 - kt2)
     b = 1.0 / (p2 - pt2 - kt2)
+    return (ptz, pty, ptx), a, b
+
+
+def green_apply(g: Grid, W: np.ndarray, kt2: complex, factors=None) -> np.ndarray:
+    """G W = F^-1 [G^(p) . F W]  for a vector field W [3, nz, ny, nx].
+
+    Applies the 3x3 Sherman-Morrison tensor mode by mode (same formula as
+    ``green_tensor``, written out on the broadcast grid).  factors is
+    green_factors(g, kt2), formed here when not given."""
+    (ptz, pty, ptx), a, b = factors if factors is not None else green_factors(g, kt2)
     Wh = fftn3(W)
     s = ptx * Wh[0] + pty * Wh[1] + ptz * Wh[2]      # pt . W^
     bs = b * s
@@ -363,9 +372,10 @@ def cbs(g: Grid, eps_r: np.ndarray, S: np.ndarray, tol: float = 1e-6,
     hist = []
     eta = float("inf")
     k = 0
+    gf = green_factors(g, pot.kt2)
     for k in range(1, max_iter + 1):
         W = pot.V[None] * E + S
-        GW = green_apply(g, W, pot.kt2)
+        GW = green_apply(g, W, pot.kt2, gf)
         dE = pot.gamma[None] * (GW - E)
         E = E + dE
         nd = math.sqrt(float(np.sum(dE.real ** 2 + dE.imag ** 2)))
