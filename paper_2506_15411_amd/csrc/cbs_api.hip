@@ -1822,6 +1822,7 @@ struct Scpml {
   long long N, n3;            // voxels; complex values of a vector field
   float2 *basis, *b, *F, *X, *Z;
   const float2 *A[3], *B[3], *T[3], *sinv[3];
+  bool thin[3];               // 8p <= n: A and B in the two-launch form (RA|CA, RB|CB)
   double2 *part, *h, *y;
   float2* vec(int i) const { return basis + (long long)i * n3; }
 };
@@ -1874,31 +1875,47 @@ int scpml_setup(cbs_plan_s* p, const cbs_scpml* layer, int restart, void* work, 
                        col + 4 * n, const_cast<float2*>(s.A[a]), const_cast<float2*>(s.B[a]),
                        const_cast<float2*>(s.T[a]), const_cast<float2*>(s.sinv[a]));
     HIP_LAUNCHED();
+    const int pa = p->pml[a];
+    s.thin[a] = pa > 0 && 8 * pa <= n;
+    if (s.thin[a]) {
+      const long long nt = 6LL * pa * n;
+      hipLaunchKernelGGL(k_scpml_thin, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0,
+                         p->stream, n, pa, col, col + n, col + 2 * n, col + 3 * n,
+                         const_cast<float2*>(s.A[a]), const_cast<float2*>(s.B[a]));
+      HIP_LAUNCHED();
+    }
   }
   return CBS_OK;
 }
 
-// one axis product (kMm* epilogues, see scpml.hpp) over scalar [nz][ny][nx] fields
+// one axis product (kMm* epilogues, see scpml.hpp) over scalar [nz][ny][nx] fields;
+// kMmCompact writes and kMmColFix reads the compact [lines][4p] buffer cbuf
 int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in, float2* out,
-                    float alpha, bool accumulate, int mode = kMmPlain, float2* out2 = nullptr) {
+                    float alpha, bool accumulate, int mode = kMmPlain, float2* out2 = nullptr,
+                    const float2* cbuf = nullptr) {
   AxisMM a;
   a.M = M;
   a.in = in;
   a.out = out;
   a.out2 = out2;
   a.sinv = s.sinv[axis];
+  a.aux = cbuf;
   a.n = s.dims[axis];
   a.Q = axis == 0 ? 1 : (axis == 1 ? s.dims[0] : s.dims[0] * s.dims[1]);
   a.p = s.p->pml[axis];
-  a.rows = mode == kMmLayer ? 2 * a.p : a.n;
+  a.rows = mode == kMmLayer ? 2 * a.p : (mode == kMmCompact ? 4 * a.p : a.n);
+  a.K = mode == kMmColFix ? 2 * a.p : a.n;
+  a.ldm = a.K;
+  a.cld = 4LL * a.p;
+  a.in_ld = mode == kMmColFix ? a.cld : 0;
   a.L = s.N / a.n;
   a.alpha = alpha;
   a.accumulate = accumulate ? 1 : 0;
   a.mode = mode;
-  if (a.rows <= 0) return CBS_OK;
+  if (a.rows <= 0 || a.K <= 0) return CBS_OK;
   const unsigned tiles = (unsigned)((a.L + kMmTL - 1) / kMmTL) *
                          (unsigned)((a.rows + kMmTI - 1) / kMmTI);
-  if (a.Q == 1)
+  if (a.Q == 1 || a.in_ld > 0)
     hipLaunchKernelGGL(k_axis_mm<true>, dim3(tiles), dim3(256), 0, s.p->stream, a);
   else
     hipLaunchKernelGGL(k_axis_mm<false>, dim3(tiles), dim3(256), 0, s.p->stream, a);
@@ -1906,11 +1923,23 @@ int enqueue_axis_mm(const Scpml& s, int axis, const float2* M, const float2* in,
   return CBS_OK;
 }
 
+// F_c += alpha M v_c along axis b for M = A_b (B) or B_b (!A): one dense product,
+// or on a thin layer the two launches of the split form, with X as the compact
+// buffer (X is no longer needed once every (S^-1 - I) T_c X term is formed)
+int enqueue_ab(const Scpml& s, int b, bool A, const float2* vc, float2* Fc, float alpha) {
+  const float2* M = A ? s.A[b] : s.B[b];
+  if (!s.thin[b]) return enqueue_axis_mm(s, b, M, vc, Fc, alpha, true);
+  const long long rows4 = 4LL * s.p->pml[b] * s.dims[b];   // RA (4p x n), then CA (n x 2p)
+  if (int rc = enqueue_axis_mm(s, b, M, vc, s.X, 1.0f, false, kMmCompact)) return rc;
+  return enqueue_axis_mm(s, b, M + rows4, s.X, Fc, alpha, true, kMmColFix, nullptr, s.X);
+}
+
 // F = alpha (L_s - L) v:  per component c, sum_{b != c} A_b v_c + B_c v_c +
 // T_c Z + (S_c^-1 - I) T_c X, where one product u_b = T_b v_b per axis gives
 // X = sum_b S_b^-1 u_b and Z = sum_b (S_b^-1 - I) u_b, and (S_c^-1 - I) T_c X is
 // formed on the layer rows only (an axis without a layer has A = B = 0 and
-// S^-1 = I exactly and skips those terms)
+// S^-1 = I exactly and skips those terms).  The X and Z terms of every component
+// come first, so X can serve the thin-layer products as scratch.
 int enqueue_delta(const Scpml& s, const float2* v, float2* F, float alpha) {
   const long long N = s.N;
   const int* pml = s.p->pml;
@@ -1920,14 +1949,16 @@ int enqueue_delta(const Scpml& s, const float2* v, float2* F, float alpha) {
       return rc;
   for (int c = 0; c < 3; ++c) {
     float2* Fc = F + c * N;
-    const float2* vc = v + c * N;
     if ((rc = enqueue_axis_mm(s, c, s.T[c], s.Z, Fc, alpha, false))) return rc;
     if (pml[c] > 0 && (rc = enqueue_axis_mm(s, c, s.T[c], s.X, Fc, alpha, true, kMmLayer)))
       return rc;
-    if (pml[c] > 0 && (rc = enqueue_axis_mm(s, c, s.B[c], vc, Fc, alpha, true))) return rc;
+  }
+  for (int c = 0; c < 3; ++c) {
+    float2* Fc = F + c * N;
+    const float2* vc = v + c * N;
+    if (pml[c] > 0 && (rc = enqueue_ab(s, c, false, vc, Fc, alpha))) return rc;
     for (int b = 0; b < 3; ++b)
-      if (b != c && pml[b] > 0 && (rc = enqueue_axis_mm(s, b, s.A[b], vc, Fc, alpha, true)))
-        return rc;
+      if (b != c && pml[b] > 0 && (rc = enqueue_ab(s, b, true, vc, Fc, alpha))) return rc;
   }
   return CBS_OK;
 }

@@ -16,7 +16,9 @@
 //
 // every term a 1D operator along one axis.  Each is stored as a dense n x n
 // matrix (built in FP64 on the device from the circulant columns of D, T, D^2,
-// T^2) and applied to all lines of a field by a tiled complex GEMM.  Since
+// T^2) and applied to all lines of a field by a tiled complex GEMM; on a thin
+// layer A and B are applied in a two-launch form over the layer's rows and
+// columns instead (see kMmCompact below).  Since
 // S^-1 - I vanishes outside the layer, C_c X - T_c Y is evaluated as
 // T_c Z + (S_c^-1 - I) T_c X with Z = X - Y = sum_b (S_b^-1 - I) T_b E_b: one
 // product T_b E_b per axis gives both X and Z, and T_c X is needed on the 2p
@@ -122,6 +124,36 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
   T[e] = make_float2((float)t[ij].x, (float)t[ij].y);
 }
 
+// Tables of a thin layer (8p <= n) for the two-launch form of A and B, written
+// over the dense A and B (6pn <= n^2 entries each): RA = [D[L, :]; D^2[L, :]]
+// (4p x n) then CA = D[:, L] (n x 2p), and RB, CB the same with T and T^2.
+// Layer voxel q < 2p is axis voxel q (q < p) or q + n - 2p.  One thread per
+// entry, FP64 columns rounded to FP32.
+__global__ void k_scpml_thin(int n, int p, const double2* d, const double2* t,
+                             const double2* dd, const double2* tt, float2* RA, float2* RB) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long rows = 4LL * p * n, total = 6LL * p * n;
+  if (e >= total) return;
+  auto lrow = [&](int q) { return q < p ? q : q + (n - 2 * p); };
+  double2 va, vb;
+  if (e < rows) {
+    const int r = (int)(e / n), j = (int)(e % n);
+    const bool sq = r >= 2 * p;
+    const int i = lrow(sq ? r - 2 * p : r);
+    const int ij = ((i - j) % n + n) % n;
+    va = sq ? dd[ij] : d[ij];
+    vb = sq ? tt[ij] : t[ij];
+  } else {
+    const long long e2 = e - rows;
+    const int i = (int)(e2 / (2 * p)), q = (int)(e2 % (2 * p));
+    const int ij = ((i - lrow(q)) % n + n) % n;
+    va = d[ij];
+    vb = t[ij];
+  }
+  RA[e] = make_float2((float)va.x, (float)va.y);
+  RB[e] = make_float2((float)vb.x, (float)vb.y);
+}
+
 // Products of one n x n matrix M with every line of a scalar [nz][ny][nx] field
 // along one axis of length n: element i of line l sits at (l / Q) n Q + l % Q
 // + i Q (Q = 1 along x, nx along y, nx ny along z).  With acc(l, i) = sum_j
@@ -131,17 +163,34 @@ __global__ void k_scpml_matrices(int n, int pml, const double2* d, const double2
 //   kMmLayer:  out += alpha (s_i - 1) acc, for the 2p layer rows i only
 // where s_i is 1/s at voxel i of the axis (FP32).  Tiles of 64 lines x 64
 // outputs, j staged through LDS 32 at a time.
-enum : int { kMmPlain = 0, kMmSplit = 1, kMmLayer = 2 };
+//
+// An axis whose layer is thin (8p <= n) applies A and B in two narrow products
+// instead of one dense one.  With lambda = 1 - 1/s (non-zero on the 2p layer
+// voxels L only), A = D^2 - S^-1 D S^-1 D is
+//   A v = lambda (D^2 v) + S^-1 D[:, L] (lambda_L (D v)_L)
+// (B the same with T): the layer rows of D and D^2 times v (4p rows, K = n),
+// then D's layer columns times 2p values per line (n rows, K = 2p).  The two
+// launches use
+//   kMmCompact: out[l][r] = alpha lambda acc for the 4p stacked layer rows r
+//               (D rows, then D^2 rows), a compact [lines][4p] buffer;
+//   kMmColFix:  out += alpha (s_i acc + [i in L] aux[l][2p + q(i)]), the input
+//               the first 2p values of each compact line and aux that buffer.
+enum : int { kMmPlain = 0, kMmSplit = 1, kMmLayer = 2, kMmCompact = 3, kMmColFix = 4 };
 
 struct AxisMM {
   const float2* M;
   const float2* in;
   float2* out;
   float2* out2;         // kMmSplit
-  const float2* sinv;   // kMmSplit, kMmLayer: 1/s along the axis
+  const float2* sinv;   // 1/s along the axis
+  const float2* aux;    // kMmColFix: the compact buffer of kMmCompact
   int n, Q;
-  int rows;             // output rows computed: n, or 2p for kMmLayer
-  int p;                // layer voxels per side (kMmLayer)
+  int rows;             // output rows computed: n, 2p (kMmLayer) or 4p (kMmCompact)
+  int K;                // reduction length: n, or 2p (kMmColFix)
+  int ldm;              // row stride of M
+  int p;                // layer voxels per side
+  long long in_ld;      // > 0: compact input, line l at in + l in_ld (j contiguous)
+  long long cld;        // line stride of the compact buffers (4p)
   long long L;          // lines
   float alpha;
   int accumulate;
@@ -206,7 +255,8 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   constexpr int kLineStep = 256 / kMmTJ, kJStep = 256 / kMmTL, kRowStep = 256 / kMmTJ;
   const int tj = ROWWISE ? tid % kMmTJ : tid / kMmTL;
   const long long tl = l0 + (ROWWISE ? tid / kMmTJ : tid % kMmTL);
-  const long long lbase = ROWWISE ? tl * a.n : axis_addr(tl, 0, a.n, a.Q);
+  const long long lstride = a.in_ld > 0 ? a.in_ld : (long long)a.n;   // ROWWISE line stride
+  const long long lbase = ROWWISE ? tl * lstride : axis_addr(tl, 0, a.n, a.Q);
   unsigned lok = 0;   // bit e: the line of input element e exists
 #pragma unroll
   for (int e = 0; e < kIn; ++e)
@@ -217,15 +267,15 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
 #pragma unroll
   for (int e = 0; e < kMt; ++e) {
     const int r = r0 + ti + kRowStep * e;
-    mrow[e] = (long long)mm_row(a, r < a.rows ? r : 0) * a.n;
+    mrow[e] = (long long)mm_row(a, r < a.rows ? r : 0) * a.ldm;
     if (r < a.rows) rok |= 1u << e;
   }
   auto fetch = [&](int j0) {
 #pragma unroll
     for (int e = 0; e < kIn; ++e) {
       const int j = ROWWISE ? j0 + tj : j0 + tj + kJStep * e;
-      const bool ok = ((lok >> e) & 1u) && j < a.n;
-      const long long ad = ROWWISE ? lbase + (long long)(kLineStep * e) * a.n + j
+      const bool ok = ((lok >> e) & 1u) && j < a.K;
+      const long long ad = ROWWISE ? lbase + (long long)(kLineStep * e) * lstride + j
                                    : lbase + (long long)j * a.Q;
       const float2 v = a.in[ok ? ad : 0];
       pin[e] = ok ? v : make_float2(0.f, 0.f);
@@ -233,7 +283,7 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
     const int jm = j0 + tjm;
 #pragma unroll
     for (int e = 0; e < kMt; ++e) {
-      const bool ok = ((rok >> e) & 1u) && jm < a.n;
+      const bool ok = ((rok >> e) & 1u) && jm < a.K;
       const float2 v = a.M[ok ? mrow[e] + jm : 0];
       pm[e] = ok ? v : make_float2(0.f, 0.f);
     }
@@ -253,10 +303,10 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
     }
   };
   fetch(0);
-  for (int j0 = 0; j0 < a.n; j0 += kMmTJ) {
+  for (int j0 = 0; j0 < a.K; j0 += kMmTJ) {
     stash();
     __syncthreads();
-    if (j0 + kMmTJ < a.n) fetch(j0 + kMmTJ);
+    if (j0 + kMmTJ < a.K) fetch(j0 + kMmTJ);
 #pragma unroll
     for (int ks = 0; ks < kMmTJ / 4; ++ks) {
       const int k = 4 * ks + lk;
@@ -295,12 +345,29 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
         const long long l = l0 + wl + 16 * lb + lr;
         const int rr = r0 + wi + 16 * ib + 4 * lk + q;
         if (l < a.L && rr < a.rows) {
-          const int i = mm_row(a, rr);
-          const long long o = obase[lb] + (long long)i * a.Q;
           const float re = p1[ib][lb][q] - p2[ib][lb][q];
           const float im = p3[ib][lb][q] - p1[ib][lb][q] - p2[ib][lb][q];
           const float2 v = make_float2(a.alpha * re, a.alpha * im);
-          if (a.mode == kMmPlain) {
+          if (a.mode == kMmCompact) {
+            // stacked row rr -> layer voxel q (D rows, then D^2 rows) -> axis voxel
+            const int ql = rr < 2 * a.p ? rr : rr - 2 * a.p;
+            const float2 si = a.sinv[ql < a.p ? ql : ql + (a.n - 2 * a.p)];
+            a.out[l * a.cld + rr] = cmul(make_float2(1.0f - si.x, -si.y), v);
+            continue;
+          }
+          const int i = mm_row(a, rr);
+          const long long o = obase[lb] + (long long)i * a.Q;
+          if (a.mode == kMmColFix) {
+            float2 w = cmul(a.sinv[i], v);
+            if (i < a.p || i >= a.n - a.p) {
+              const int ql = i < a.p ? i : i - (a.n - 2 * a.p);
+              const float2 z = a.aux[l * a.cld + 2 * a.p + ql];
+              w.x += a.alpha * z.x;
+              w.y += a.alpha * z.y;
+            }
+            const float2 u = a.out[o];
+            a.out[o] = make_float2(u.x + w.x, u.y + w.y);
+          } else if (a.mode == kMmPlain) {
             float2 w = v;
             if (a.accumulate) {
               const float2 u = a.out[o];
