@@ -1,8 +1,11 @@
 """The stretched-coordinate absorbing layer (reference [31] of the paper's
 simulation-setup paragraph) on the GPU, against the FP64 oracle.
 
-* The layer's operator (L_s - L) v: per-axis dense products on the GPU, FFT
-  derivatives in the oracle (oracle.scpml.delta_apply), on even and odd axes.
+* The layer's operator (L_s - L) v: per-axis matrix products on the GPU, FFT
+  derivatives in the oracle (oracle.scpml.delta_apply), on even and odd axes,
+  through both forms of A and B: dense (y on 24 x 20 x 32, z on 25 x 27 x 15)
+  and the two-launch form of a thin layer, 8p <= n (x and z on 24 x 20 x 32, x
+  on 25 x 27 x 15; z in the reflection cases).
 * Equal GMRES steps: two restart cycles of GMRES(8) on the CBS-preconditioned
   system, GPU (FP32 fields, FP64 reductions) against scipy's GMRES on the
   oracle's operator (oracle.scpml.gmres_solve).
