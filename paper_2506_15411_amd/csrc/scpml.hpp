@@ -336,6 +336,25 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
   long long obase[2];
 #pragma unroll
   for (int lb = 0; lb < 2; ++lb) obase[lb] = axis_addr(l0 + wl + 16 * lb + lr, 0, a.n, a.Q);
+  // Epilogue in two phases: the values of out that the outputs add to are all
+  // loaded first, so one thread's loads are in flight together instead of each
+  // waiting behind the previous output's store (out2 and the compact buffer,
+  // read by fewer outputs, are loaded in the second phase).
+  const bool add_out = a.mode == kMmColFix || a.mode == kMmLayer ||
+                       (a.accumulate && (a.mode == kMmPlain || a.mode == kMmSplit));
+  float2 u1[2][2][4];
+#pragma unroll
+  for (int ib = 0; ib < 2; ++ib)
+#pragma unroll
+    for (int lb = 0; lb < 2; ++lb)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const long long l = l0 + wl + 16 * lb + lr;
+        const int rr = r0 + wi + 16 * ib + 4 * lk + q;
+        u1[ib][lb][q] = make_float2(0.f, 0.f);
+        if (add_out && l < a.L && rr < a.rows)
+          u1[ib][lb][q] = a.out[obase[lb] + (long long)mm_row(a, rr) * a.Q];
+      }
 #pragma unroll
   for (int ib = 0; ib < 2; ++ib)
 #pragma unroll
@@ -348,6 +367,7 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
           const float re = p1[ib][lb][q] - p2[ib][lb][q];
           const float im = p3[ib][lb][q] - p1[ib][lb][q] - p2[ib][lb][q];
           const float2 v = make_float2(a.alpha * re, a.alpha * im);
+          const float2 u = u1[ib][lb][q];
           if (a.mode == kMmCompact) {
             // stacked row rr -> layer voxel q (D rows, then D^2 rows) -> axis voxel
             const int ql = rr < 2 * a.p ? rr : rr - 2 * a.p;
@@ -359,43 +379,25 @@ __global__ void __launch_bounds__(256) k_axis_mm(AxisMM a) {
           const long long o = obase[lb] + (long long)i * a.Q;
           if (a.mode == kMmColFix) {
             float2 w = cmul(a.sinv[i], v);
-            if (i < a.p || i >= a.n - a.p) {
+            if (i < a.p || i >= a.n - a.p) {   // the compact D^2 term on the layer rows
               const int ql = i < a.p ? i : i - (a.n - 2 * a.p);
               const float2 z = a.aux[l * a.cld + 2 * a.p + ql];
               w.x += a.alpha * z.x;
               w.y += a.alpha * z.y;
             }
-            const float2 u = a.out[o];
             a.out[o] = make_float2(u.x + w.x, u.y + w.y);
           } else if (a.mode == kMmPlain) {
-            float2 w = v;
-            if (a.accumulate) {
-              const float2 u = a.out[o];
-              w.x += u.x;
-              w.y += u.y;
-            }
-            a.out[o] = w;
-          } else {
+            a.out[o] = make_float2(v.x + u.x, v.y + u.y);
+          } else if (a.mode == kMmLayer) {
             const float2 si = a.sinv[i];
-            const float2 dm = make_float2(si.x - 1.0f, si.y);   // 1/s - 1
-            float2 w2 = cmul(dm, v);
-            if (a.mode == kMmLayer || a.accumulate) {
-              const float2 u = a.mode == kMmLayer ? a.out[o] : a.out2[o];
-              w2.x += u.x;
-              w2.y += u.y;
-            }
-            if (a.mode == kMmLayer) {
-              a.out[o] = w2;
-            } else {
-              float2 w = cmul(si, v);
-              if (a.accumulate) {
-                const float2 u = a.out[o];
-                w.x += u.x;
-                w.y += u.y;
-              }
-              a.out[o] = w;
-              a.out2[o] = w2;
-            }
+            const float2 w2 = cmul(make_float2(si.x - 1.0f, si.y), v);   // (1/s - 1) acc
+            a.out[o] = make_float2(w2.x + u.x, w2.y + u.y);
+          } else {   // kMmSplit
+            const float2 si = a.sinv[i];
+            const float2 w = cmul(si, v), w2 = cmul(make_float2(si.x - 1.0f, si.y), v);
+            const float2 u2 = a.accumulate ? a.out2[o] : make_float2(0.f, 0.f);
+            a.out[o] = make_float2(w.x + u.x, w.y + u.y);
+            a.out2[o] = make_float2(w2.x + u2.x, w2.y + u2.y);
           }
         }
       }
