@@ -5,7 +5,9 @@ simulation-setup paragraph) on the GPU, against the FP64 oracle.
   derivatives in the oracle (oracle.scpml.delta_apply), on even and odd axes,
   through both forms of A and B: dense (y on 24 x 20 x 32, z on 25 x 27 x 15)
   and the two-launch form of a thin layer, 8p <= n (x and z on 24 x 20 x 32, x
-  on 25 x 27 x 15; z in the reflection cases).
+  on 25 x 27 x 15; z in the reflection cases); and at the 275 x 275 x 315
+  lens size on fields that vary along one axis only, against the oracle's
+  operator on a grid of that axis alone.
 * Equal GMRES steps: two restart cycles of GMRES(8) on the CBS-preconditioned
   system, GPU (FP32 fields, FP64 reductions) against scipy's GMRES on the
   oracle's operator (oracle.scpml.gmres_solve).
@@ -65,6 +67,44 @@ def test_layer_operator_matches_oracle(shape, pml, device):
         assert err < 2e-6
     # no stretch: the operator is exactly zero
     assert torch.count_nonzero(p.scpml_operator(vd, 0.0, 2)).item() == 0
+    p.close()
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_layer_operator_at_the_lens_size_on_one_axis_fields(axis, device):
+    """At the 275 x 275 x 315 size of the 16 um lens (lambda/16: thin 8-voxel x
+    and y layers, a thick 48-voxel z layer, in the launch configuration of its
+    solves): a field that varies along one axis only has no derivative along
+    the other two, so (L_s - L) v is the one-axis operator applied along every
+    line, whatever the other layers.  The oracle applies it on a grid of that
+    axis alone (2 voxels and no layer on the others); every line of the GPU
+    result must match it."""
+    shape, pml, pitch = (275, 275, 315), (8, 8, 48), LAM / 16
+    n = shape[axis]
+    dims, lp = [2, 2, 2], [0, 0, 0]
+    dims[axis], lp[axis] = n, pml[axis]
+    g1 = oc.Grid(*dims, pitch, LAM, 1.0, tuple(lp), sigma_max=0.0)
+    rng = np.random.default_rng(11 + axis)
+    line = (rng.standard_normal((3, n)) + 1j * rng.standard_normal((3, n))).astype(np.complex64)
+    bshape = [3, 1, 1, 1]
+    bshape[3 - axis] = n                      # field layout [c][z][y][x]
+    v1 = np.broadcast_to(line.reshape(bshape), (3,) + g1.vshape).astype(np.complex128)
+    p = plan(shape, pml, device, pitch=pitch)
+    vd = torch.from_numpy(line).to(device).reshape(bshape).expand((3,) + p.vshape).contiguous()
+    for alpha, order in ((0.75, 1), (1.5, 2)):
+        ref1 = scpml.delta_apply(g1, v1, alpha, order)
+        sel = [slice(None), 0, 0, 0]
+        sel[3 - axis] = slice(None)
+        ref_line = ref1[tuple(sel)]
+        assert np.allclose(ref1, ref_line.reshape(bshape), rtol=0, atol=1e-9 * np.abs(ref1).max())
+        out = p.scpml_operator(vd, alpha, order)
+        exp = torch.from_numpy(ref_line.astype(np.complex64)).to(device).reshape(bshape)
+        num = torch.linalg.vector_norm((out - exp).to(torch.complex128)).item()
+        den = torch.linalg.vector_norm(exp.expand_as(out).to(torch.complex128)).item()
+        print(f"axis {axis} (n {n}, layer {pml[axis]}), alpha {alpha} order {order}: "
+              f"rel {num / den:.2e} over {out.numel() // 3} voxels")
+        assert num / den < 5e-6
+        del out, exp
     p.close()
 
 
